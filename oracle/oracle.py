@@ -1,0 +1,359 @@
+"""Plain FP64 CPU oracle for the twisted-mass disconnected-loop method.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no
+code with the HIP implementation in ``paper_1401_6749_amd`` and imports
+nothing from it.
+
+The heavy loops (hopping term, even-odd CG, Philox, contractions) are in
+``tm_oracle.c`` (plain C99 complex arithmetic, built with gcc into
+``libtm_oracle.so``); this file wraps them and adds the small host-side steps
+in NumPy:
+
+  * ``gamma`` / ``gammas16``    chiral basis and the 16 local insertions
+  * ``project``                 spin matrices -> local, one-derivative and
+                                symmetrised gamma_mu D_nu loops
+  * ``tsm_combine``             the truncated-solver estimator (Sec. 2.1,
+                                Eq. estiTSM) and its stochastic variance
+  * ``loops_tsm``               the whole path: Z4 sources (Sec. 2), HP and LP
+                                solves (Sec. 2.1), contractions at all
+                                timeslices (Sec. 2.2), projection and TSM.
+
+Array layouts (complex128): spinor (V, 4, 3), gauge (V, 4, 3, 3), with
+lex = x + Lx*(y + Ly*(z + Lz*t)).  ``a`` always means 2*kappa*mu.
+
+Pins for every function are in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tm_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libtm_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile tm_oracle.c with gcc (OpenMP) into libtm_oracle.so."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", _SRC, "-o", tmp, "-lm"]
+        )
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.orc_gamma.argtypes = [ctypes.c_int, dp]
+        L.orc_dhop.argtypes = [ip, ctypes.c_int, dp, dp, dp]
+        L.orc_apply_M.argtypes = [ip, ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
+        L.orc_apply_mhat.argtypes = L.orc_apply_M.argtypes
+        L.orc_cg_eo.argtypes = [ip, ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, dp, dp,
+                                ctypes.c_double, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_cg_eo.restype = ctypes.c_int
+        L.orc_solve.argtypes = [ip, ctypes.c_int, dp, ctypes.c_double, ctypes.c_double, dp, dp,
+                                ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp]
+        L.orc_solve.restype = ctypes.c_int
+        L.orc_philox4x64_10.argtypes = [u64p, u64p, u64p]
+        L.orc_z4_source.argtypes = [ip, ctypes.c_uint64, ctypes.c_uint64, dp]
+        L.orc_contract.argtypes = [ip, ctypes.c_int, dp, dp, dp, dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dims(dims):
+    d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+    assert d.shape == (4,) and all(int(x) >= 2 and int(x) % 2 == 0 for x in d), dims
+    return d
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def volume(dims) -> int:
+    return int(np.prod([int(x) for x in dims]))
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# ----------------------------------------------------------------------------
+# Gamma matrices and the 16 local insertions
+# ----------------------------------------------------------------------------
+def gamma(mu: int) -> np.ndarray:
+    """gamma_{mu+1} for mu = 0..3, gamma_5 for mu = 4 (oracle's own table)."""
+    out = np.zeros((4, 4, 2))
+    lib().orc_gamma(int(mu), _dp(out))
+    return out[..., 0] + 1j * out[..., 1]
+
+
+GAMMA_NAMES = [
+    "1", "g1", "g2", "g3", "g4", "g5", "g1g5", "g2g5", "g3g5", "g4g5",
+    "s12", "s13", "s14", "s23", "s24", "s34",
+]
+
+
+def gammas16() -> np.ndarray:
+    """The 16 local insertions in the order 1, g1..g4, g5, g1g5..g4g5,
+    s12, s13, s14, s23, s24, s34 with s_mn = (i/2)[g_m, g_n]."""
+    g = [gamma(m) for m in range(5)]
+    out = [np.eye(4, dtype=np.complex128)]
+    out += [g[m] for m in range(4)]
+    out.append(g[4])
+    out += [g[m] @ g[4] for m in range(4)]
+    for m in range(4):
+        for n in range(m + 1, 4):
+            out.append(0.5j * (g[m] @ g[n] - g[n] @ g[m]))
+    return np.array(out)
+
+
+# ----------------------------------------------------------------------------
+# Operators (Sec. 2.2 twisted-mass operator; Sec. 2.4 hopping term)
+# ----------------------------------------------------------------------------
+def dhop(dims, tbc, U, psi):
+    """D_hop psi (full lattice)."""
+    d = _dims(dims)
+    v = volume(d)
+    U = _c(U, (v, 4, 3, 3))
+    psi = _c(psi, (v, 4, 3))
+    out = np.empty_like(psi)
+    lib().orc_dhop(_ip(d), int(tbc), _dp(U), _dp(psi), _dp(out))
+    return out
+
+
+def apply_M(dims, tbc, U, kappa, a, psi, dag=False):
+    """M psi = psi - kappa D_hop psi + i a g5 psi (or M^dag psi)."""
+    d = _dims(dims)
+    v = volume(d)
+    U = _c(U, (v, 4, 3, 3))
+    psi = _c(psi, (v, 4, 3))
+    out = np.empty_like(psi)
+    lib().orc_apply_M(_ip(d), int(tbc), _dp(U), float(kappa), float(a), int(bool(dag)), _dp(psi), _dp(out))
+    return out
+
+
+def apply_mhat(dims, tbc, U, kappa, a, psi, dag=False):
+    """Even-odd Schur operator on the even sublattice (odd sites of the
+    input are ignored, odd sites of the output are zero)."""
+    d = _dims(dims)
+    v = volume(d)
+    U = _c(U, (v, 4, 3, 3))
+    psi = _c(psi, (v, 4, 3))
+    out = np.empty_like(psi)
+    lib().orc_apply_mhat(_ip(d), int(tbc), _dp(U), float(kappa), float(a), int(bool(dag)), _dp(psi), _dp(out))
+    return out
+
+
+def cg_eo(dims, tbc, U, kappa, a, bhat, tol=1e-10, max_iter=100000, fixed_iters=0):
+    """CG on Mhat^dag Mhat x = Mhat^dag bhat (zero start). Returns (x, iters, relres)."""
+    d = _dims(dims)
+    v = volume(d)
+    U = _c(U, (v, 4, 3, 3))
+    b = _c(bhat, (v, 4, 3))
+    x = np.empty_like(b)
+    rr = np.zeros(1)
+    it = lib().orc_cg_eo(_ip(d), int(tbc), _dp(U), float(kappa), float(a), _dp(b), _dp(x),
+                         float(tol), int(max_iter), int(fixed_iters), _dp(rr))
+    return x, int(it), float(rr[0])
+
+
+def solve(dims, tbc, U, kappa, a, eta, tol=1e-10, max_iter=100000, fixed_iters=0):
+    """Solve M s = eta by even-odd CG. Returns (s, iters, cg_relres, true_relres)."""
+    d = _dims(dims)
+    v = volume(d)
+    U = _c(U, (v, 4, 3, 3))
+    e = _c(eta, (v, 4, 3))
+    s = np.empty_like(e)
+    rr = np.zeros(1)
+    tr = np.zeros(1)
+    it = lib().orc_solve(_ip(d), int(tbc), _dp(U), float(kappa), float(a), _dp(e), _dp(s),
+                         float(tol), int(max_iter), int(fixed_iters), _dp(rr), _dp(tr))
+    return s, int(it), float(rr[0]), float(tr[0])
+
+
+# ----------------------------------------------------------------------------
+# Z4 noise (Sec. 2: Z_N sources, Eq. 1-2; Z4 used in this work)
+# ----------------------------------------------------------------------------
+def philox4x64_10(counter, key):
+    c = (ctypes.c_uint64 * 4)(*[int(x) & (2**64 - 1) for x in counter])
+    k = (ctypes.c_uint64 * 2)(*[int(x) & (2**64 - 1) for x in key])
+    o = (ctypes.c_uint64 * 4)()
+    lib().orc_philox4x64_10(c, k, o)
+    return [int(o[i]) for i in range(4)]
+
+
+def z4_source(dims, seed, src):
+    """Z4 noise vector eta (V, 4, 3): entries ((+-1) + i(+-1))/sqrt(2)."""
+    d = _dims(dims)
+    v = volume(d)
+    out = np.empty((v, 4, 3), dtype=np.complex128)
+    lib().orc_z4_source(_ip(d), ctypes.c_uint64(int(seed)), ctypes.c_uint64(int(src)), _dp(out))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Contractions, projection, TSM
+# ----------------------------------------------------------------------------
+def contract(dims, tbc, U, eta, s):
+    """Spin matrices per timeslice, shape (9, T, 4, 4): kind 0 local,
+    1..4 forward F^nu, 5..8 backward B^nu (nu = x, y, z, t)."""
+    d = _dims(dims)
+    v = volume(d)
+    U = _c(U, (v, 4, 3, 3))
+    e = _c(eta, (v, 4, 3))
+    s = _c(s, (v, 4, 3))
+    out = np.empty((9, int(d[3]), 4, 4), dtype=np.complex128)
+    lib().orc_contract(_ip(d), int(tbc), _dp(U), _dp(e), _dp(s), _dp(out))
+    return out
+
+
+N_LOCAL = 16
+N_DERIV = 64
+N_SYM = 10
+N_OPS = N_LOCAL + N_DERIV + N_SYM
+SYM_PAIRS = [(m, n) for m in range(4) for n in range(m, 4)]
+
+
+def project(P):
+    """Spin matrices (9, T, 4, 4) -> operator loops (90, T) complex.
+
+    ops 0..15         L_G(t)      = sum_ab G_ab P_ab(t)              (local, eta^dag G s)
+    ops 16+4g+nu      L^D_{G,nu}  = 1/4 [F(t) + F(t-d) - B(t) - B(t-d)],
+                      d = 1 for the time direction and 0 otherwise (t-1 mod T):
+                      the symmetric covariant derivative attributed to x.
+    ops 80..89        O_mn = (L^D_{g_m,n} + L^D_{g_n,m}) / 2 for m <= n.
+    """
+    P = np.asarray(P)
+    G = gammas16()
+    T = P.shape[1]
+    out = np.zeros((N_OPS, T), dtype=np.complex128)
+    proj = np.einsum("gab,ktab->gkt", G, P)  # (16, 9, T)
+    out[:N_LOCAL] = proj[:, 0]
+    for g in range(16):
+        for nu in range(4):
+            F = proj[g, 1 + nu]
+            B = proj[g, 5 + nu]
+            if nu == 3:
+                Fs, Bs = np.roll(F, 1), np.roll(B, 1)  # value at t-1
+            else:
+                Fs, Bs = F, B
+            out[N_LOCAL + 4 * g + nu] = 0.25 * (F + Fs - B - Bs)
+    for i, (m, n) in enumerate(SYM_PAIRS):
+        out[N_LOCAL + N_DERIV + i] = 0.5 * (out[N_LOCAL + 4 * (1 + m) + n] + out[N_LOCAL + 4 * (1 + n) + m])
+    return out
+
+
+def _svar(x, axis=0):
+    n = x.shape[axis]
+    if n < 2:
+        return np.full(np.delete(x.shape, axis), np.nan)
+    return np.var(x, axis=axis, ddof=1)
+
+
+def tsm_combine(hp, lp_corr, lp_bulk):
+    """Truncated-solver estimator (Sec. 2.1, Eq. estiTSM) per operator and t.
+
+    hp, lp_corr: (N_HP, ...) loops of the correction set (same sources, HP and
+    LP solves); lp_bulk: (N_LP, ...) LP-only loops of the other sources.
+      est = mean(hp - lp_corr) + mean(lp_bulk)
+      var = s^2(hp - lp_corr)/N_HP + s^2(lp_bulk)/N_LP, real and imaginary
+            parts separately, sample variances with n-1.
+    A set with no members contributes 0 to both; a set with one member makes
+    its variance NaN.
+    Returns (est complex, var_re, var_im).
+    """
+    hp = np.asarray(hp)
+    lp_corr = np.asarray(lp_corr)
+    lp_bulk = np.asarray(lp_bulk)
+    n_hp = hp.shape[0]
+    n_lp = lp_bulk.shape[0]
+    shape = (hp if n_hp else lp_bulk).shape[1:]
+    est = np.zeros(shape, dtype=np.complex128)
+    vre = np.zeros(shape)
+    vim = np.zeros(shape)
+    if n_hp:
+        d = hp - lp_corr
+        est = est + d.mean(axis=0)
+        vre = vre + _svar(d.real) / n_hp
+        vim = vim + _svar(d.imag) / n_hp
+    if n_lp:
+        est = est + lp_bulk.mean(axis=0)
+        vre = vre + _svar(lp_bulk.real) / n_lp
+        vim = vim + _svar(lp_bulk.imag) / n_lp
+    return est, vre, vim
+
+
+def loops_tsm(dims, tbc, U, kappa, a, noise_seed, n_hp, n_lp, hp_tol=1e-10, lp_tol=1e-2,
+              max_iter=100000, lp_fixed_iters=0, source_ids=None, return_raw=False):
+    """The whole path on the CPU in FP64.
+
+    Source ids 0..n_hp-1 form the correction set (HP and LP solves of the same
+    eta_j), ids n_hp..n_hp+n_lp-1 the bulk set (LP only), as in Eq. estiTSM.
+    LP solves are FP64 solves truncated at lp_tol (or lp_fixed_iters
+    iterations); HP solves run to hp_tol.  ``source_ids`` restricts the work to
+    a subset (for timing samples); then the estimator is not formed.
+
+    Returns dict with est (90, T), var_re, var_im, per-source loops
+    hp (n_hp, 90, T), lp (n_hp+n_lp, 90, T), iteration counts and timings.
+    """
+    T = int(dims[3])
+    ids = list(range(n_hp + n_lp)) if source_ids is None else list(source_ids)
+    hp_loops, lp_loops, hp_raw, lp_raw = {}, {}, {}, {}
+    hp_iters, lp_iters = {}, {}
+    t0 = time.perf_counter()
+    for j in ids:
+        eta = z4_source(dims, noise_seed, j)
+        if j < n_hp:
+            s, it, _, _ = solve(dims, tbc, U, kappa, a, eta, tol=hp_tol, max_iter=max_iter)
+            P = contract(dims, tbc, U, eta, s)
+            hp_raw[j] = P
+            hp_loops[j] = project(P)
+            hp_iters[j] = it
+        s, it, _, _ = solve(dims, tbc, U, kappa, a, eta, tol=lp_tol, max_iter=max_iter,
+                            fixed_iters=lp_fixed_iters)
+        P = contract(dims, tbc, U, eta, s)
+        lp_raw[j] = P
+        lp_loops[j] = project(P)
+        lp_iters[j] = it
+    wall = time.perf_counter() - t0
+    res = {"hp_iters": hp_iters, "lp_iters": lp_iters, "seconds": wall,
+           "hp_loops": hp_loops, "lp_loops": lp_loops}
+    if return_raw:
+        res["hp_raw"] = hp_raw
+        res["lp_raw"] = lp_raw
+    if source_ids is None:
+        hp = np.array([hp_loops[j] for j in range(n_hp)]).reshape(n_hp, N_OPS, T)
+        lpc = np.array([lp_loops[j] for j in range(n_hp)]).reshape(n_hp, N_OPS, T)
+        lpb = np.array([lp_loops[j] for j in range(n_hp, n_hp + n_lp)]).reshape(n_lp, N_OPS, T)
+        est, vre, vim = tsm_combine(hp, lpc, lpb)
+        res.update(est=est, var_re=vre, var_im=vim)
+    return res
