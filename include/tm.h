@@ -1,0 +1,318 @@
+/*
+ * tm.h - C ABI of the MI355X twisted-mass disconnected-loop library (libtm).
+ *
+ * The library computes stochastic estimates of quark loops with the
+ * truncated solver method of Alexandrou, Drach, Jansen, Koutsou, Vaquero,
+ * "Computation of disconnected contributions to nucleon observables"
+ * (LATTICE 2013):
+ *   - Z4 noise sources eta_j                         (Sec. 2, Eq. 1-2; Z4 noise)
+ *   - solves M s_j = eta_j, M_E^-1 = (1/N) sum s eta^dag  (Sec. 2, Eq. estiM)
+ *   - CG inversions, truncated for low precision     (Sec. 2.1, LP residual ~1e-2)
+ *   - the TSM estimator                              (Sec. 2.1, Eq. estiTSM)
+ *   - loops at every insertion time                  (Sec. 2.2, last paragraph)
+ * for the twisted-mass Wilson operator
+ *   M = 1 - kappa*D_hop + i*a*gamma5,   a = 2*kappa*mu,
+ * i.e. M = B^-1 + H with B = (1 + i a gamma5)^-1 and H = -kappa*D_hop, the
+ * split used in the hopping-parameter expansion (Sec. 2.4, Eq. HPE), with
+ *   D_hop psi(x) = sum_mu (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                       + (1 + gamma_mu) U_mu(x-mu)^dagger psi(x-mu).
+ *
+ * Conventions (the paper fixes none of them):
+ *   lattice dims  {Lx, Ly, Lz, Lt}, every extent even and >= 2
+ *   site index    lex = x + Lx*(y + Ly*(z + Lz*t)); parity (x+y+z+t) mod 2
+ *   time BC       hops across t = Lt-1 <-> 0 carry t_bc (-1 antiperiodic)
+ *   gammas        chiral Euclidean basis, gamma5 = diag(1, 1, -1, -1)
+ *   canonical spinor  double[V][4 spin][3 colour][2 re,im]
+ *   canonical gauge   double[V][4 mu][3 row][3 col][2 re,im]
+ *
+ * Errors: every call returns a tm_status; no exception crosses the ABI.
+ * tm_last_error() gives the message of the last failing call on a context.
+ * Device pointers are HIP device addresses on the context's device; host
+ * pointers are ordinary host memory.  The caller owns every buffer it
+ * passes; the library owns contexts, gauge handles and serving engines
+ * until the matching destroy/free call.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tm_context tm_context;
+typedef struct tm_gauge tm_gauge;
+typedef struct tm_server tm_server;
+
+typedef enum tm_status {
+    TM_OK = 0,
+    TM_ERR_ARG = -1,     /* invalid argument (shape, null pointer, alias, unloaded precision) */
+    TM_ERR_NOMEM = -2,   /* device allocation failed or exceeds the context's HBM budget */
+    TM_ERR_HIP = -3,     /* a HIP runtime call failed */
+    TM_ERR_NOCONV = -4,  /* a solve hit max_iter before its tolerance (outputs still written) */
+    TM_ERR_NUMERIC = -5, /* NaN/Inf or a non-positive <p, A p> met in a solve */
+    TM_ERR_STATE = -6    /* call not valid in the object's current state */
+} tm_status;
+
+/* Storage precisions.  Spinors and links in F16/BF16 are used by the
+ * low-precision solver only; their arithmetic is FP32. */
+typedef enum tm_prec {
+    TM_PREC_F64 = 1,
+    TM_PREC_F32 = 2,
+    TM_PREC_F16 = 4,
+    TM_PREC_BF16 = 8
+} tm_prec;
+
+/* Operators for tm_dslash.  HOP, M, MDAG act on full-lattice fields; the
+ * MHAT family acts on the even half (the even-odd Schur complement
+ *   Mhat = A - kappa^2 D_eo A^-1 D_oe,  A = 1 + i a gamma5,
+ * with D_eo the hop from odd to even sites). */
+typedef enum tm_op {
+    TM_OP_HOP = 0,          /* out = D_hop in */
+    TM_OP_M = 1,            /* out = M in */
+    TM_OP_MDAG = 2,         /* out = M^dagger in = gamma5 M(-mu) gamma5 in */
+    TM_OP_MHAT = 3,         /* out_e = Mhat in_e */
+    TM_OP_MHAT_DAG = 4,     /* out_e = Mhat^dagger in_e */
+    TM_OP_MHAT_DAG_MHAT = 5 /* out_e = Mhat^dagger Mhat in_e */
+} tm_op;
+
+/* Solver modes (Sec. 2.1: low- and high-precision inversions by CG). */
+typedef enum tm_solve_mode {
+    TM_SOLVE_F64 = 0,   /* plain FP64 CG throughout */
+    TM_SOLVE_MIXED = 1, /* FP32 CG with FP64 reliable updates of x and the true residual */
+    TM_SOLVE_LP = 2     /* half-precision (F16 or BF16) operands, FP32 x and r, FP32 math */
+} tm_solve_mode;
+
+/* Device allocator used for every library allocation.  NULL means hipMalloc
+ * and hipFree.  The Python binding passes torch's caching allocator. */
+typedef void *(*tm_alloc_fn)(size_t bytes, int device, void *user);
+typedef void (*tm_free_fn)(void *ptr, int device, void *user);
+
+/* ------------------------------------------------------------------ */
+/* Context                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hbm_budget (bytes) bounds the
+ * device memory the context may hold at once (0 = no bound).  Ownership of
+ * *out passes to the caller until tm_destroy.  Errors: TM_ERR_ARG (null
+ * out, bad device), TM_ERR_HIP. */
+int tm_create(int device, size_t hbm_budget, tm_alloc_fn alloc, tm_free_fn free_fn, void *user,
+              tm_context **out);
+
+/* Release every gauge field and workspace of the context, then the context. */
+int tm_destroy(tm_context *ctx);
+
+/* Message of the last failing call on ctx (owned by ctx; "" if none). */
+const char *tm_last_error(const tm_context *ctx);
+
+/* Bytes currently held on the device by ctx, and the peak since creation. */
+int tm_memory_usage(const tm_context *ctx, size_t *in_use, size_t *peak);
+
+/* ------------------------------------------------------------------ */
+/* Gauge field (the configuration the loops are measured on, Sec. 3)   */
+/* ------------------------------------------------------------------ */
+
+/* Upload a gauge field and build the device layouts for each precision in
+ * prec_mask (bitwise OR of tm_prec; F64 is always built: it serves the
+ * reconstruction, the true residual and the contractions).
+ *   dims        {Lx, Ly, Lz, Lt}, each even and >= 2
+ *   links_host  host, canonical gauge layout, V*4*9 complex doubles
+ *   t_bc        -1 antiperiodic or +1 periodic in time
+ * Every link is checked for unitarity and det = 1 (|U^dag U - 1| and
+ * |det U - 1| below 1e-10); links are stored as their first two rows.
+ * The caller keeps links_host; the library owns the device copies until
+ * tm_free_gauge.  Synchronous.  Errors: TM_ERR_ARG (dims, t_bc, non-SU(3)
+ * link, NaN), TM_ERR_NOMEM, TM_ERR_HIP. */
+int tm_load_gauge(tm_context *ctx, const int dims[4], const double *links_host, int t_bc,
+                  unsigned prec_mask, tm_gauge **out);
+
+int tm_free_gauge(tm_context *ctx, tm_gauge *gauge);
+
+/* Bytes of one field in the library's device layout for precision prec:
+ * subset 0 = one parity (V/2 sites), 1 = full lattice.  0 on bad input.
+ * Layout (site-major structure of arrays over the V/2 sites of a parity,
+ * site cb = lex/2 within its parity, full field = even half then odd half):
+ *   F64   12 complex components k = 3*spin+colour, component k at [k][V/2] (16 B each)
+ *   F32   6 float4 groups (components 2g, 2g+1) at [g][V/2]
+ *   F16/BF16  3 groups of 8 halves (components 4g..4g+3) at [g][V/2], then a
+ *         float per-site scale [V/2]; value = half * scale. */
+size_t tm_field_bytes(const tm_gauge *gauge, tm_prec prec, int subset);
+
+/* Convert nrhs full-lattice fields between the canonical spinor layout
+ * (device, FP64) and the device layout of prec.  Asynchronous on
+ * hip_stream (a hipStream_t, NULL = default stream).  Errors: TM_ERR_ARG. */
+int tm_field_import(tm_context *ctx, const tm_gauge *gauge, tm_prec prec, int nrhs,
+                    const double *canonical_dev, void *field_dev, void *hip_stream);
+int tm_field_export(tm_context *ctx, const tm_gauge *gauge, tm_prec prec, int nrhs,
+                    const void *field_dev, double *canonical_dev, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Dirac operator (Sec. 2.2 twisted-mass operator; Sec. 2.4 H)          */
+/* ------------------------------------------------------------------ */
+
+/* Apply op to nrhs fields in the device layout of prec (full-lattice
+ * fields for HOP/M/MDAG, even-half fields for the MHAT family), fields
+ * contiguous one after another.  kappa and two_kappa_mu = a as in M above.
+ * in and out must not overlap.  Asynchronous on hip_stream; no host sync.
+ * Errors: TM_ERR_ARG (nrhs < 1 or > 16, aliasing, prec not loaded). */
+int tm_dslash(tm_context *ctx, const tm_gauge *gauge, tm_op op, double kappa, double two_kappa_mu,
+              tm_prec prec, int nrhs, const void *in, void *out, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Solver (Sec. 2.1: "the inverter, a CG solver")                       */
+/* ------------------------------------------------------------------ */
+
+typedef struct tm_solver_params {
+    int mode;              /* tm_solve_mode */
+    int half_prec;         /* TM_PREC_F16 or TM_PREC_BF16 for TM_SOLVE_LP */
+    double tol;            /* stop at |r_k| <= tol*|r_0| on Mhat^dag Mhat x = Mhat^dag bhat */
+    int max_iter;          /* iteration cap (TM_ERR_NOCONV when reached) */
+    int fixed_iters;       /* > 0: run exactly this many iterations, ignore tol */
+    double delta;          /* MIXED: reliable update when |r| < delta*|r at last update| (0 -> 0.1) */
+    int chunk;             /* iterations per device launch chunk between host checks (0 -> auto) */
+} tm_solver_params;
+
+typedef struct tm_solve_stats {
+    int iters;             /* CG iterations */
+    int reliable_updates;  /* MIXED: number of FP64 reliable updates */
+    double cg_rel_resid;   /* |r_k| / |r_0| of the iterated residual at exit */
+    double true_rel_resid; /* |eta - M s| / |eta| recomputed in FP64 at exit */
+    double seconds;        /* wall time of the whole call */
+} tm_solve_stats;
+
+/* Solve M x_i = b_i for nrhs full-lattice right-hand sides through
+ * even-odd CG on Mhat^dag Mhat with zero initial guess:
+ *   bhat_e = b_e + kappa D_eo A^-1 b_o,  CG for x_e,
+ *   x_o = A^-1 (b_o + kappa D_oe x_e).
+ * b, x: device, canonical spinor layout, nrhs fields each.  stats: host
+ * array [nrhs] or NULL.  Runs on hip_stream and synchronises at exit.
+ * Errors: TM_ERR_ARG, TM_ERR_NOMEM, TM_ERR_NOCONV (x and stats still
+ * written), TM_ERR_NUMERIC. */
+int tm_cg_solve(tm_context *ctx, const tm_gauge *gauge, double kappa, double two_kappa_mu,
+                const tm_solver_params *params, int nrhs, const double *b, double *x,
+                tm_solve_stats *stats, void *hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Noise (Sec. 2: Z_N noise with Eq. 1-2; Z4 here)                      */
+/* ------------------------------------------------------------------ */
+
+/* Write the Z4 source eta(seed, src_id) in the canonical spinor layout to
+ * the device buffer out: eta(x)_{3*spin+colour} = ((-1)^b0 + i (-1)^b1)/sqrt(2)
+ * with b0, b1 bits 2k, 2k+1 of word 0 of Philox4x64-10(counter = (lex,
+ * src_id, 0, 0), key = (seed, 0)).  Asynchronous on hip_stream. */
+int tm_z4_source(tm_context *ctx, const int dims[4], uint64_t seed, uint64_t src_id, double *out,
+                 void *hip_stream);
+
+/* ------------------------------------------------------------------ */
+/* Loops with the truncated solver method (Sec. 2.1 Eq. estiTSM, 2.2)   */
+/* ------------------------------------------------------------------ */
+
+#define TM_N_LOCAL 16 /* 1, g1..g4, g5, g1g5..g4g5, s12, s13, s14, s23, s24, s34 */
+#define TM_N_DERIV 64 /* L^D_{G,nu}: index 16 + 4*G + nu, nu = x, y, z, t */
+#define TM_N_SYM 10   /* (L^D_{g_m,n} + L^D_{g_n,m})/2, m <= n: index 80.. */
+#define TM_N_OPS 90
+
+typedef struct tm_tsm_params {
+    double kappa;
+    double two_kappa_mu;
+    uint64_t noise_seed;
+    int n_hp;                  /* correction set: source ids 0..n_hp-1, HP and LP solves */
+    int n_lp;                  /* bulk set: ids n_hp..n_hp+n_lp-1, LP solves only */
+    tm_solver_params hp;       /* high-precision solver (usually MIXED or F64 to 1e-10) */
+    tm_solver_params lp;       /* low-precision solver (usually LP truncated at 1e-2) */
+    int batch;                 /* right-hand sides per multi-RHS launch (1..16, 0 -> 12) */
+    int want_true_resid;       /* 1: compute |eta - M s|/|eta| for every solve */
+} tm_tsm_params;
+
+typedef struct tm_tsm_stats {
+    int hp_solves, lp_solves;
+    long long hp_iters, lp_iters;        /* summed over solves */
+    int hp_max_iters, lp_max_iters;
+    int reliable_updates;
+    double max_hp_true_resid;            /* over HP solves, if want_true_resid */
+    double max_lp_true_resid;
+    double seconds, hp_seconds, lp_seconds;
+} tm_tsm_stats;
+
+/* The whole path for one gauge field: Z4 sources, HP and LP solves,
+ * contractions at all timeslices, projection onto the 90 operators and the
+ * TSM combination
+ *   est = (1/N_HP) sum_{j<N_HP} (L_j^HP - L_j^LP) + (1/N_LP) sum_{j>=N_HP} L_j^LP
+ *   var = s^2(L^HP - L^LP)/N_HP + s^2(L^LP)/N_LP   (re and im separately, n-1),
+ * a set with no members contributing 0 and a set with one member making
+ * var NaN.  n_hp = 0 gives the plain estimator (Sec. 2, Eq. estiM).
+ * Loops are the raw traces eta^dag G s (local) and the symmetric covariant
+ * derivative L^D_{G,nu}(t) = 1/4 [F(t) + F(t - d) - B(t) - B(t - d)],
+ *   F(t) = sum_{x in t} eta(x)^dag G U_nu(x) s(x+nu),
+ *   B(t) = sum_{x in t} eta(x+nu)^dag G U_nu(x)^dagger s(x),
+ * d = 1 for nu = t else 0; no factor 2 kappa, i or fermion-loop sign.
+ * Outputs (host): est [TM_N_OPS][Lt][2], var_re and var_im [TM_N_OPS][Lt];
+ * raw (optional, NULL to skip) [n_hp + (n_hp + n_lp)][9][Lt][4][4][2]: HP
+ * spin matrices of ids 0..n_hp-1, then LP ones of ids 0..n_hp+n_lp-1, kinds
+ * 0 local, 1..4 F^nu, 5..8 B^nu, entry [a][b] = sum eta*_a (...) s_b.
+ * Synchronous.  Errors: TM_ERR_ARG, TM_ERR_NOMEM, TM_ERR_NOCONV (outputs
+ * still written), TM_ERR_NUMERIC. */
+int tm_loops_tsm(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *params, double *est,
+                 double *var_re, double *var_im, double *raw, tm_tsm_stats *stats);
+
+/* Project spin matrices [n][9][Lt][4][4][2] (host) onto the 90 operator
+ * loops [n][TM_N_OPS][Lt][2] (host), as in tm_loops_tsm. */
+int tm_project_loops(int n, int lt, const double *raw, double *ops);
+
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching of loop requests                        */
+/* ------------------------------------------------------------------ */
+
+typedef struct tm_request {
+    const tm_gauge *gauge;     /* resident gauge field (any loaded lattice) */
+    tm_tsm_params params;      /* kappa, mu, seeds, N_HP, N_LP, solvers */
+    uint64_t tag;              /* caller's identifier, returned with the result */
+} tm_request;
+
+typedef struct tm_result {
+    uint64_t tag;
+    int status;                /* tm_status of the request */
+    int lt;
+    double *est;               /* [TM_N_OPS][lt][2], owned by the server until tm_result_free */
+    double *var_re, *var_im;   /* [TM_N_OPS][lt] */
+    tm_tsm_stats stats;
+    double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock */
+} tm_result;
+
+/* Start a serving engine on ctx.  slots = right-hand sides per multi-RHS
+ * batch (1..16); workspace_budget = device bytes the engine may hold for
+ * solver workspaces (requests wait until their footprint fits).  A worker
+ * thread runs the loop: admission by footprint, packing of sources that
+ * share a gauge field and precision into batches, refill of finished slots
+ * between chunks, contraction and TSM combination per request. */
+int tm_serve_create(tm_context *ctx, int slots, size_t workspace_budget, tm_server **out);
+/* Queue a request (copied).  Errors: TM_ERR_ARG, TM_ERR_NOMEM (the
+ * request's footprint can never fit the workspace budget). */
+int tm_serve_submit(tm_server *srv, const tm_request *req);
+/* Pop up to max finished results into out[] (returns the count, or < 0). */
+int tm_serve_poll(tm_server *srv, tm_result *out, int max);
+/* Block until every submitted request is finished. */
+int tm_serve_drain(tm_server *srv);
+void tm_result_free(tm_result *res);
+/* Seconds on the server clock (same clock as tm_result times). */
+double tm_serve_clock(tm_server *srv);
+int tm_serve_destroy(tm_server *srv);
+
+/* ------------------------------------------------------------------ */
+/* Measurement helpers                                                 */
+/* ------------------------------------------------------------------ */
+
+/* Copy `bytes` from src to dst (device) with the library's streaming copy
+ * kernel, the measured HBM ceiling for the roofline.  Asynchronous. */
+int tm_stream_copy(tm_context *ctx, const void *src, void *dst, size_t bytes, void *hip_stream);
+
+/* Host-side self checks of the library's index arithmetic (no GPU needed):
+ * returns 0 when they pass. */
+int tm_selftest(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TM_H */

@@ -1,0 +1,338 @@
+// CG scalar kernels (FP64, fixed-order reductions of per-block partials),
+// site-local vector kernels, conversions between storage precisions and the
+// streaming copy probe.
+#include "tm_dev.h"
+#include "tm_launch.h"
+
+namespace tmk {
+
+// Fixed-order sum of n doubles by one block of BLOCK threads: thread i sums
+// v[i], v[i+BLOCK], ... sequentially, then the block tree.  Valid in thread 0.
+__device__ __forceinline__ double sum_fixed(const double *v, int n, double *lds)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += BLOCK) s += v[i];
+    return block_sum<BLOCK>(s, lds);
+}
+
+__device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1.0e300; }
+
+__global__ __launch_bounds__(BLOCK) void k_cg_alpha(SlotState *st, const double *partial, int nblk)
+{
+    __shared__ double lds[BLOCK / 64];
+    const int slot = blockIdx.x;
+    SlotState &S = st[slot];
+    if (S.status != ST_RUNNING) return;
+    const double pap = sum_fixed(partial + (size_t)slot * nblk, nblk, lds);
+    if (threadIdx.x == 0) {
+        S.pap = pap;
+        if (!finite_pos(pap)) {
+            S.status = ST_NUMERIC;
+            S.alpha = 0.0;
+        } else {
+            S.alpha = S.rr / pap;
+        }
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_cg_beta(SlotState *st, const double *partial, int nblk)
+{
+    __shared__ double lds[BLOCK / 64];
+    const int slot = blockIdx.x;
+    SlotState &S = st[slot];
+    if (S.status != ST_RUNNING) return;
+    const double rr = sum_fixed(partial + (size_t)slot * nblk, nblk, lds);
+    if (threadIdx.x == 0) {
+        S.iter += 1;
+        S.rr_new = rr;
+        if (!(rr >= 0.0 && rr < 1.0e300)) {
+            S.status = ST_NUMERIC;
+        } else if (S.tol2 > 0.0 && rr <= S.tol2 * S.rr0) {
+            // mixed precision confirms convergence on the true residual
+            S.status = S.mixed ? ST_NEED_UPDATE : ST_CONVERGED;
+            if (!S.mixed) S.rr = rr;
+        } else if (S.mixed && rr <= S.delta2 * S.rr_ref) {
+            S.status = ST_NEED_UPDATE;
+        } else if (S.iter >= S.max_iter) {
+            S.status = ST_MAXITER;
+            S.rr = rr;
+        } else {
+            S.beta = rr / S.rr;
+            S.rr = rr;
+        }
+    }
+}
+
+__global__ void k_slot_start(SlotState *st, const double *partial, int nblk, double kappa, double a, double tol2,
+                             int max_iter, double delta2, int mixed)
+{
+    __shared__ double lds[BLOCK / 64];
+    const double rr0 = sum_fixed(partial, nblk, lds);
+    if (threadIdx.x == 0) {
+        SlotState &S = *st;
+        S.kappa = kappa;
+        S.a = a;
+        S.tol2 = tol2;
+        S.max_iter = max_iter;
+        S.delta2 = delta2;
+        S.mixed = mixed;
+        S.iter = 0;
+        S.rr0 = rr0;
+        S.rr = rr0;
+        S.rr_new = rr0;
+        S.rr_ref = rr0;
+        S.alpha = S.beta = S.pap = 0.0;
+        if (!(rr0 >= 0.0 && rr0 < 1.0e300))
+            S.status = ST_NUMERIC;
+        else if (rr0 == 0.0)
+            S.status = ST_CONVERGED;
+        else if (max_iter <= 0)
+            S.status = ST_MAXITER;
+        else
+            S.status = ST_RUNNING;
+    }
+}
+
+__global__ void k_reliable_finish(SlotState *st, const double *partial, int nblk)
+{
+    __shared__ double lds[BLOCK / 64];
+    const double rr = sum_fixed(partial, nblk, lds);
+    if (threadIdx.x == 0) {
+        SlotState &S = *st;
+        S.rr_new = rr;
+        if (!(rr >= 0.0 && rr < 1.0e300)) {
+            S.status = ST_NUMERIC;
+        } else if (S.tol2 > 0.0 && rr <= S.tol2 * S.rr0) {
+            S.status = ST_CONVERGED;
+            S.rr = rr;
+        } else if (S.iter >= S.max_iter) {
+            S.status = ST_MAXITER;
+            S.rr = rr;
+        } else {
+            S.beta = rr / S.rr;
+            S.rr = rr;
+            S.rr_ref = rr;
+            S.status = ST_RUNNING;
+        }
+    }
+}
+
+__global__ void k_reduce(const double *partial, int nblk, double *out)
+{
+    __shared__ double lds[BLOCK / 64];
+    const double v = sum_fixed(partial + (size_t)blockIdx.x * nblk, nblk, lds);
+    if (threadIdx.x == 0) out[blockIdx.x] = v;
+}
+
+void launch_cg_alpha(SlotState *st, const double *partial, int nslot, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_alpha, dim3(nslot), dim3(BLOCK), 0, s, st, partial, nblk);
+}
+void launch_cg_beta(SlotState *st, const double *partial, int nslot, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cg_beta, dim3(nslot), dim3(BLOCK), 0, s, st, partial, nblk);
+}
+void launch_slot_start(SlotState *st, const double *partial, int nblk, double kappa, double a, double tol2,
+                       int max_iter, double delta2, int mixed, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_slot_start, dim3(1), dim3(BLOCK), 0, s, st, partial, nblk, kappa, a, tol2, max_iter,
+                       delta2, mixed);
+}
+void launch_reliable_finish(SlotState *st, const double *partial, int nblk, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reliable_finish, dim3(1), dim3(BLOCK), 0, s, st, partial, nblk);
+}
+void launch_reduce(const double *partial, int nblk, int n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(n), dim3(BLOCK), 0, s, partial, nblk, out);
+}
+
+// ---------------------------------------------------------------------------
+// p = r + beta p
+// ---------------------------------------------------------------------------
+template <int SP, int XR>
+__global__ __launch_bounds__(BLOCK) void k_p_update(Geom g, char *p, size_t p_slot, const char *r, size_t r_slot,
+                                                    SlotState *st, int nslot, int nblk, int swz)
+{
+    using T = typename Real<SP>::T;
+    int sblk, slot;
+    if (!map_block(nblk, nslot, swz, sblk, slot)) return;
+    const SlotState &S = st[slot];
+    if (S.status != ST_RUNNING) return;
+    const int cb = sblk * BLOCK + threadIdx.x;
+    if (cb >= g.vh) return;
+    const T beta = (T)S.beta;
+    cpx<T> pv[12], rv[12];
+    char *ps = p + (size_t)slot * p_slot;
+    SpinorIO<SP>::load(ps, g.vh, cb, pv);
+    SpinorIO<XR>::load(r + (size_t)slot * r_slot, g.vh, cb, rv);
+#pragma unroll
+    for (int k = 0; k < 12; k++) pv[k] = rv[k] + cscale(beta, pv[k]);
+    SpinorIO<SP>::store(ps, g.vh, cb, pv);
+}
+
+void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot,
+                     SlotState *st, int nslot, int swz, hipStream_t s)
+{
+    const int nblk = nblk_of(g);
+    const int total = nblk * nslot;
+    const int grid = swz ? 8 * ((total + 7) / 8) : total;
+#define TMK_P(SP, XR)                                                                                   \
+    if (sp == SP && xr == XR) {                                                                        \
+        hipLaunchKernelGGL((k_p_update<SP, XR>), dim3(grid), dim3(BLOCK), 0, s, g, p, p_slot, r, r_slot, \
+                           st, nslot, nblk, swz);                                                       \
+        return;                                                                                         \
+    }
+    TMK_P(P64, P64)
+    TMK_P(P32, P32)
+    TMK_P(P16, P32)
+    TMK_P(PBF, P32)
+#undef TMK_P
+}
+
+// ---------------------------------------------------------------------------
+// Conversions and site-local kernels
+// ---------------------------------------------------------------------------
+template <int PI, int PO>
+__global__ __launch_bounds__(BLOCK) void k_convert(Geom g, const char *in, size_t in_slot, char *out,
+                                                   size_t out_slot)
+{
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    if (cb >= g.vh) return;
+    const int slot = blockIdx.y;
+    cpx<double> v[12];
+    SpinorIO<PI>::load(in + (size_t)slot * in_slot, g.vh, cb, v);
+    SpinorIO<PO>::store(out + (size_t)slot * out_slot, g.vh, cb, v);
+}
+
+template <int PI>
+static void conv_from(int pout, const Geom &g, const char *in, size_t is, char *out, size_t os, int nslot,
+                      hipStream_t s)
+{
+    dim3 grid(nblk_of(g), nslot);
+    switch (pout) {
+    case P64: hipLaunchKernelGGL((k_convert<PI, P64>), grid, dim3(BLOCK), 0, s, g, in, is, out, os); break;
+    case P32: hipLaunchKernelGGL((k_convert<PI, P32>), grid, dim3(BLOCK), 0, s, g, in, is, out, os); break;
+    case P16: hipLaunchKernelGGL((k_convert<PI, P16>), grid, dim3(BLOCK), 0, s, g, in, is, out, os); break;
+    case PBF: hipLaunchKernelGGL((k_convert<PI, PBF>), grid, dim3(BLOCK), 0, s, g, in, is, out, os); break;
+    }
+}
+
+void launch_convert(int pin, int pout, const Geom &g, const char *in, size_t in_slot, char *out, size_t out_slot,
+                    int nslot, hipStream_t s)
+{
+    switch (pin) {
+    case P64: conv_from<P64>(pout, g, in, in_slot, out, out_slot, nslot, s); break;
+    case P32: conv_from<P32>(pout, g, in, in_slot, out, out_slot, nslot, s); break;
+    case P16: conv_from<P16>(pout, g, in, in_slot, out, out_slot, nslot, s); break;
+    case PBF: conv_from<PBF>(pout, g, in, in_slot, out, out_slot, nslot, s); break;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k_zero(Geom g, char *f, size_t slot_bytes)
+{
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    if (cb >= g.vh) return;
+    cpx<double> v[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) v[k] = cpx<double>{0.0, 0.0};
+    SpinorIO<P>::store(f + (size_t)blockIdx.y * slot_bytes, g.vh, cb, v);
+}
+
+void launch_zero(int p, const Geom &g, char *f, size_t slot, int nslot, hipStream_t s)
+{
+    dim3 grid(nblk_of(g), nslot);
+    switch (p) {
+    case P64: hipLaunchKernelGGL((k_zero<P64>), grid, dim3(BLOCK), 0, s, g, f, slot); break;
+    case P32: hipLaunchKernelGGL((k_zero<P32>), grid, dim3(BLOCK), 0, s, g, f, slot); break;
+    case P16: hipLaunchKernelGGL((k_zero<P16>), grid, dim3(BLOCK), 0, s, g, f, slot); break;
+    case PBF: hipLaunchKernelGGL((k_zero<PBF>), grid, dim3(BLOCK), 0, s, g, f, slot); break;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_accum_x(Geom g, char *x64, const char *x32, char *x32z)
+{
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    if (cb >= g.vh) return;
+    cpx<double> a[12], b[12];
+    SpinorIO<P64>::load(x64, g.vh, cb, a);
+    SpinorIO<P32>::load(x32, g.vh, cb, b);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        a[k] = a[k] + b[k];
+        b[k] = cpx<double>{0.0, 0.0};
+    }
+    SpinorIO<P64>::store(x64, g.vh, cb, a);
+    if (x32z) SpinorIO<P32>::store(x32z, g.vh, cb, b);
+}
+
+void launch_accum_x(const Geom &g, char *x64, const char *x32_in, char *x32_zero, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_accum_x, dim3(nblk_of(g)), dim3(BLOCK), 0, s, g, x64, x32_in, x32_zero);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_norm_partial(Geom g, const char *f, double *partial)
+{
+    __shared__ double lds[BLOCK / 64];
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    double part = 0.0;
+    if (cb < g.vh) {
+        cpx<double> v[12];
+        SpinorIO<P64>::load(f, g.vh, cb, v);
+#pragma unroll
+        for (int k = 0; k < 12; k++) part += norm2(v[k]);
+    }
+    part = block_sum<BLOCK>(part, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = part;
+}
+
+void launch_norm_partial(const Geom &g, const char *f, double *partial, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_norm_partial, dim3(nblk_of(g)), dim3(BLOCK), 0, s, g, f, partial);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_site_diag(Geom g, int mode, double a, const char *in, char *out)
+{
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    if (cb >= g.vh) return;
+    cpx<double> v[12];
+    SpinorIO<P64>::load(in, g.vh, cb, v);
+    if (mode == 1) {
+        const double den = 1.0 / (1.0 + a * a);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const double ch = k < 6 ? 1.0 : -1.0;
+            v[k] = cmul(cpx<double>{den, -ch * a * den}, v[k]);
+        }
+    }
+    SpinorIO<P64>::store(out, g.vh, cb, v);
+}
+
+void launch_site_diag(const Geom &g, int mode, double a, const char *in, char *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_site_diag, dim3(nblk_of(g)), dim3(BLOCK), 0, s, g, mode, a, in, out);
+}
+
+// ---------------------------------------------------------------------------
+// Streaming copy (16-byte vectors, grid-stride): the measured HBM ceiling.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                       size_t n)
+{
+    size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * BLOCK;
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+void launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const size_t n = bytes / 16;
+    size_t blocks = (n + BLOCK - 1) / BLOCK;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(BLOCK), 0, s, (const uint4 *)src, (uint4 *)dst,
+                       n);
+}
+
+}  // namespace tmk

@@ -1,0 +1,385 @@
+// Z4 noise from a counter-based generator, loop contractions at every
+// timeslice, projection onto the local / one-derivative insertions and the
+// truncated-solver combination.
+#include "tm_dev.h"
+#include "tm_launch.h"
+
+namespace tmk {
+
+// ---------------------------------------------------------------------------
+// Z4 noise
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLOCK) void k_z4_codes(Geom g, uint64_t seed, uint64_t src, uint32_t *codes)
+{
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    const int par = blockIdx.y;
+    if (cb >= g.vh) return;
+    const Site s = site_of(g, cb, par);
+    codes[(size_t)par * g.vh + cb] = z4_code(lex_of(g, s), src, seed);
+}
+
+void launch_z4_codes(const Geom &g, uint64_t seed, uint64_t src, uint32_t *codes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_z4_codes, dim3(nblk_of(g), 2), dim3(BLOCK), 0, s, g, seed, src, codes);
+}
+
+#define TM_RSQRT2 0.70710678118654752440
+
+__global__ __launch_bounds__(BLOCK) void k_z4_field(Geom g, const uint32_t *codes, int ainv, double a, char *out)
+{
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    if (cb >= g.vh) return;
+    const uint32_t c = codes[cb];
+    cpx<double> v[12];
+    const double den = 1.0 / (1.0 + a * a);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        cpx<double> e = z4_unscaled<double>(c, k);
+        e = cpx<double>{e.re * TM_RSQRT2, e.im * TM_RSQRT2};
+        if (ainv) {
+            const double ch = k < 6 ? 1.0 : -1.0;
+            e = cmul(cpx<double>{den, -ch * a * den}, e);
+        }
+        v[k] = e;
+    }
+    SpinorIO<P64>::store(out, g.vh, cb, v);
+}
+
+void launch_z4_field(const Geom &g, const uint32_t *codes_par, int ainv, double a, char *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_z4_field, dim3(nblk_of(g)), dim3(BLOCK), 0, s, g, codes_par, ainv, a, out);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_z4_canonical(Geom g, uint64_t seed, uint64_t src, double *out)
+{
+    const size_t lex = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (lex >= (size_t)2 * g.vh) return;
+    const uint32_t c = z4_code(lex, src, seed);
+    double2 *o = (double2 *)out + 12 * lex;
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const cpx<double> e = z4_unscaled<double>(c, k);
+        o[k] = make_double2(e.re * TM_RSQRT2, e.im * TM_RSQRT2);
+    }
+}
+
+void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out, hipStream_t s)
+{
+    const size_t v = (size_t)2 * g.vh;
+    hipLaunchKernelGGL(k_z4_canonical, dim3((unsigned)((v + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, g, seed, src,
+                       out);
+}
+
+// ---------------------------------------------------------------------------
+// Contractions.  A block owns a chunk of CPB sites of one timeslice (both
+// parities); each thread accumulates its sites, the block reduces in a fixed
+// order and writes one partial per (timeslice, chunk); a second kernel sums
+// the chunks of each timeslice in order.  Accumulators hold unscaled noise
+// (+-1 +- i); the factor 2^-1/2 is applied once at the end.
+//   kind 0:      P_ab  = sum conj(eta_a) . s_b
+//   kind 1+nu:   F_ab  = sum conj(eta_a(x)) . [U_nu(x) s(x+nu)]_b
+//   kind 5+nu:   B_ab  = sum conj([U_nu(x) eta(x+nu)]_a) . s_b(x)
+// ---------------------------------------------------------------------------
+constexpr int CT = 128;        // threads per contraction block
+constexpr int SPT = 4;         // sites per thread
+constexpr int CPB = CT * SPT;  // sites per block
+
+int contract_nchunk(const Geom &g) { return (2 * g.v3h + CPB - 1) / CPB; }
+
+// reduce NV doubles across the block (fixed order) and write them to dst
+template <int NV>
+__device__ __forceinline__ void block_write(double (&acc)[NV], double *lds, double *dst)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        const double v = wave_sum(acc[k]);
+        if (l == 0) lds[w * NV + k] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NV; k += CT) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < CT / 64; q++) s += lds[q * NV + k];
+        dst[k] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ bool contract_site(const Geom &g, int t, int q, int &par, int &cb)
+{
+    if (q >= 2 * g.v3h) return false;
+    par = q < g.v3h ? 0 : 1;
+    cb = t * g.v3h + (q - par * g.v3h);
+    return true;
+}
+
+template <int NU>
+__device__ __forceinline__ void contract_dir(const Geom &g, const void *G, const char *s_fld[2],
+                                             const uint32_t *codes, int t, int chunk, double (&acc)[64])
+{
+    for (int k = 0; k < SPT; k++) {
+        int par, cb;
+        if (!contract_site(g, t, chunk * CPB + k * CT + threadIdx.x, par, cb)) continue;
+        const Site s = site_of(g, cb, par);
+        const int nf = nbr<NU, 1>(g, s);
+        const uint32_t ce = codes[(size_t)par * g.vh + cb];
+        const uint32_t cf = codes[(size_t)(1 - par) * g.vh + nf];
+        Link<double> L;
+        LinkIO<P64>::load(G, g.vh, par, NU, cb, L);
+        const double sg = (NU == 3 && g.tbc < 0 && s.t == g.L[3] - 1) ? -1.0 : 1.0;
+        const double2 *sn = (const double2 *)s_fld[1 - par];
+        const double2 *sx = (const double2 *)s_fld[par];
+        // F: conj(eta_a(x)) . (U s(x+nu))_b
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            cpx<double> h[3], w[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const double2 q = sn[(size_t)(3 * b + c) * g.vh + nf];
+                h[c] = cpx<double>{sg * q.x, sg * q.y};
+            }
+            umul(L, h, w);
+#pragma unroll
+            for (int a = 0; a < 4; a++) {
+                cpx<double> f = cmulc(z4_unscaled<double>(ce, 3 * a), w[0]) +
+                                cmulc(z4_unscaled<double>(ce, 3 * a + 1), w[1]) +
+                                cmulc(z4_unscaled<double>(ce, 3 * a + 2), w[2]);
+                acc[2 * (4 * a + b)] += f.re;
+                acc[2 * (4 * a + b) + 1] += f.im;
+            }
+        }
+        // B: conj((U eta(x+nu))_a) . s_b(x)
+        cpx<double> sv[12];
+        SpinorIO<P64>::load(sx, g.vh, cb, sv);
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            cpx<double> e[3], v[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                const cpx<double> z = z4_unscaled<double>(cf, 3 * a + c);
+                e[c] = cpx<double>{sg * z.re, sg * z.im};
+            }
+            umul(L, e, v);
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                cpx<double> f = cmulc(v[0], sv[3 * b]) + cmulc(v[1], sv[3 * b + 1]) + cmulc(v[2], sv[3 * b + 2]);
+                acc[32 + 2 * (4 * a + b)] += f.re;
+                acc[32 + 2 * (4 * a + b) + 1] += f.im;
+            }
+        }
+    }
+}
+
+// partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
+__global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd,
+                                                 const uint32_t *codes, double *cpart, int nchunk)
+{
+    __shared__ double lds[(CT / 64) * 64];
+    const int t = blockIdx.x / nchunk, chunk = blockIdx.x - t * nchunk;
+    const char *s_fld[2] = {s_even, s_odd};
+    double *dst = cpart + (size_t)blockIdx.x * 288;
+    {  // local
+        double acc[32];
+#pragma unroll
+        for (int k = 0; k < 32; k++) acc[k] = 0.0;
+        for (int k = 0; k < SPT; k++) {
+            int par, cb;
+            if (!contract_site(g, t, chunk * CPB + k * CT + threadIdx.x, par, cb)) continue;
+            const uint32_t ce = codes[(size_t)par * g.vh + cb];
+            cpx<double> sv[12];
+            SpinorIO<P64>::load(s_fld[par], g.vh, cb, sv);
+#pragma unroll
+            for (int a = 0; a < 4; a++)
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    cpx<double> f = cmulc(z4_unscaled<double>(ce, 3 * a), sv[3 * b]) +
+                                    cmulc(z4_unscaled<double>(ce, 3 * a + 1), sv[3 * b + 1]) +
+                                    cmulc(z4_unscaled<double>(ce, 3 * a + 2), sv[3 * b + 2]);
+                    acc[2 * (4 * a + b)] += f.re;
+                    acc[2 * (4 * a + b) + 1] += f.im;
+                }
+        }
+        block_write<32>(acc, lds, dst);
+    }
+#define TMK_DIR(NU)                                                        \
+    {                                                                      \
+        double acc[64];                                                    \
+        _Pragma("unroll") for (int k = 0; k < 64; k++) acc[k] = 0.0;       \
+        contract_dir<NU>(g, G, s_fld, codes, t, chunk, acc);               \
+        double tmp[32];                                                    \
+        _Pragma("unroll") for (int k = 0; k < 32; k++) tmp[k] = acc[k];    \
+        block_write<32>(tmp, lds, dst + (1 + NU) * 32);                    \
+        _Pragma("unroll") for (int k = 0; k < 32; k++) tmp[k] = acc[32 + k]; \
+        block_write<32>(tmp, lds, dst + (5 + NU) * 32);                    \
+    }
+    TMK_DIR(0)
+    TMK_DIR(1)
+    TMK_DIR(2)
+    TMK_DIR(3)
+#undef TMK_DIR
+}
+
+// raw[kind][t][ab][2] = 2^-1/2 * sum_chunk cpart[t][chunk][kind][ab][2]
+__global__ void k_contract_final(const double *cpart, int nchunk, int lt, double *raw)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over lt * 288
+    if (i >= lt * 288) return;
+    const int t = i / 288, e = i - t * 288;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; c++) s += cpart[((size_t)t * nchunk + c) * 288 + e];
+    const int kind = e / 32, ab = e - kind * 32;
+    raw[((size_t)kind * lt + t) * 32 + ab] = s * TM_RSQRT2;
+}
+
+void launch_contract(const Geom &g, const void *gauge64, const char *s_even, const char *s_odd,
+                     const uint32_t *codes, double *cpart, double *raw_out, hipStream_t s)
+{
+    const int nchunk = contract_nchunk(g);
+    const int lt = g.L[3];
+    hipLaunchKernelGGL(k_contract, dim3(lt * nchunk), dim3(CT), 0, s, g, gauge64, s_even, s_odd, codes, cpart,
+                       nchunk);
+    const int n = lt * 288;
+    hipLaunchKernelGGL(k_contract_final, dim3((n + 255) / 256), dim3(256), 0, s, cpart, nchunk, lt, raw_out);
+}
+
+// ---------------------------------------------------------------------------
+// Projection: ops[n][op][t][2] from raw[n][kind][t][16][2].
+//   op g < 16:        sum_a phase(g,a) * P[a][col(g,a)]
+//   op 16 + 4g + nu:  1/4 [F(t) + F(t-d) - B(t) - B(t-d)], d = (nu == 3)
+//   op 80 + i:        (L^D_{g_m, n} + L^D_{g_n, m}) / 2 over m <= n
+// ---------------------------------------------------------------------------
+struct GammaTab {
+    int e[16][4];
+};
+
+__device__ __forceinline__ cpx<double> gproj(const GammaTab &G, int gi, const double *m)
+{
+    // sum_a phase(a) * P[a][col(a)], phase = i^ph
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const int e = G.e[gi][a];
+        const int col = e & 3, ph = (e >> 2) & 3;
+        const double vr = m[2 * (4 * a + col)], vi = m[2 * (4 * a + col) + 1];
+        const double cr = ph == 0 ? 1.0 : ph == 2 ? -1.0 : 0.0;
+        const double ci = ph == 1 ? 1.0 : ph == 3 ? -1.0 : 0.0;
+        re += cr * vr - ci * vi;
+        im += cr * vi + ci * vr;
+    }
+    return cpx<double>{re, im};
+}
+
+__device__ __forceinline__ cpx<double> deriv_op(const GammaTab &G, const double *raw, int lt, int gi, int nu,
+                                                int t)
+{
+    const double *F = raw + ((size_t)(1 + nu) * lt) * 32;
+    const double *B = raw + ((size_t)(5 + nu) * lt) * 32;
+    const int tm = nu == 3 ? (t == 0 ? lt - 1 : t - 1) : t;
+    cpx<double> f0 = gproj(G, gi, F + (size_t)t * 32), f1 = gproj(G, gi, F + (size_t)tm * 32);
+    cpx<double> b0 = gproj(G, gi, B + (size_t)t * 32), b1 = gproj(G, gi, B + (size_t)tm * 32);
+    cpx<double> s = (f0 + f1) - (b0 + b1);
+    return cpx<double>{0.25 * s.re, 0.25 * s.im};
+}
+
+__global__ void k_project(int n, int lt, const double *raw, double *ops, GammaTab G)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)n * 90 * lt) return;
+    const int t = (int)(i % lt);
+    const int op = (int)((i / lt) % 90);
+    const size_t src = i / ((size_t)lt * 90);
+    const double *r = raw + src * 9 * lt * 32;
+    cpx<double> v;
+    if (op < 16) {
+        v = gproj(G, op, r + (size_t)t * 32);
+    } else if (op < 80) {
+        const int k = op - 16;
+        v = deriv_op(G, r, lt, k / 4, k % 4, t);
+    } else {
+        int idx = op - 80, m = 0, nn = 0;
+        for (int a = 0, c = 0; a < 4; a++)
+            for (int b = a; b < 4; b++, c++)
+                if (c == idx) {
+                    m = a;
+                    nn = b;
+                }
+        cpx<double> x = deriv_op(G, r, lt, 1 + m, nn, t), y = deriv_op(G, r, lt, 1 + nn, m, t);
+        v = cpx<double>{0.5 * (x.re + y.re), 0.5 * (x.im + y.im)};
+    }
+    ops[2 * i] = v.re;
+    ops[2 * i + 1] = v.im;
+}
+
+void launch_project(int n, int lt, const double *raw, double *ops, const int *gtab_host, hipStream_t s)
+{
+    GammaTab G;
+    for (int g = 0; g < 16; g++)
+        for (int a = 0; a < 4; a++) G.e[g][a] = gtab_host[4 * g + a];
+    const size_t total = (size_t)n * 90 * lt;
+    if (total == 0) return;
+    hipLaunchKernelGGL(k_project, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, n, lt, raw, ops, G);
+}
+
+// ---------------------------------------------------------------------------
+// TSM: est = mean(hp - lp_corr) + mean(lp_bulk); var = s^2/N of each set
+// (real and imaginary parts separately, n - 1; NaN for one member).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mean_var(int n, const double *a, const double *b, size_t stride, size_t off,
+                                         double m[2], double v[2])
+{
+    m[0] = m[1] = v[0] = v[1] = 0.0;
+    if (n == 0) return;
+    for (int j = 0; j < n; j++) {
+        double x0 = a[j * stride + off], x1 = a[j * stride + off + 1];
+        if (b) {
+            x0 -= b[j * stride + off];
+            x1 -= b[j * stride + off + 1];
+        }
+        m[0] += x0;
+        m[1] += x1;
+    }
+    m[0] /= n;
+    m[1] /= n;
+    if (n < 2) {
+        v[0] = v[1] = __builtin_nan("");
+        return;
+    }
+    double s0 = 0.0, s1 = 0.0;
+    for (int j = 0; j < n; j++) {
+        double x0 = a[j * stride + off], x1 = a[j * stride + off + 1];
+        if (b) {
+            x0 -= b[j * stride + off];
+            x1 -= b[j * stride + off + 1];
+        }
+        s0 += (x0 - m[0]) * (x0 - m[0]);
+        s1 += (x1 - m[1]) * (x1 - m[1]);
+    }
+    v[0] = s0 / (n - 1) / n;
+    v[1] = s1 / (n - 1) / n;
+}
+
+__global__ void k_tsm(int n_hp, int n_lp, int lt, const double *hp, const double *lpc, const double *lpb,
+                      double *est, double *vre, double *vim)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over 90 * lt
+    if (i >= 90 * lt) return;
+    const size_t stride = (size_t)90 * lt * 2, off = (size_t)2 * i;
+    double m1[2], v1[2], m2[2], v2[2];
+    mean_var(n_hp, hp, lpc, stride, off, m1, v1);
+    mean_var(n_lp, lpb, nullptr, stride, off, m2, v2);
+    est[2 * i] = m1[0] + m2[0];
+    est[2 * i + 1] = m1[1] + m2[1];
+    vre[i] = v1[0] + v2[0];
+    vim[i] = v1[1] + v2[1];
+}
+
+void launch_tsm_combine(int n_hp, int n_lp, int lt, const double *ops_hp, const double *ops_lp_corr,
+                        const double *ops_lp_bulk, double *est, double *var_re, double *var_im, hipStream_t s)
+{
+    const int n = 90 * lt;
+    hipLaunchKernelGGL(k_tsm, dim3((n + 127) / 128), dim3(128), 0, s, n_hp, n_lp, lt, ops_hp, ops_lp_corr,
+                       ops_lp_bulk, est, var_re, var_im);
+}
+
+}  // namespace tmk

@@ -1,0 +1,137 @@
+// Host-side internals of libtm: context, gauge handles and the slot engine
+// that runs many independent CG solves ("slots") in multi-RHS launches.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "tm.h"
+#include "tm_launch.h"
+#include "tm_types.h"
+
+struct tm_context {
+    int device = 0;
+    size_t budget = 0;
+    size_t in_use = 0, peak = 0;
+    tm_alloc_fn alloc = nullptr;
+    tm_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    std::mutex mu;  // allocation table and error string
+    std::unordered_map<void *, size_t> allocs;
+    std::string err;
+    int swz = 1;         // XCD-aware block mapping
+    int use_graphs = 1;  // capture CG chunks in hipGraphs
+    // scratch of tm_dslash (grown on demand)
+    void *op_tmp = nullptr;
+    size_t op_tmp_bytes = 0;
+};
+
+struct tm_gauge {
+    tm_context *ctx = nullptr;
+    int dims[4] = {0, 0, 0, 0};
+    int tbc = -1;
+    tmk::Geom g;
+    unsigned precs = 0;  // bit (1 << P) per built precision
+    void *links[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace tmi {
+
+int set_err(tm_context *c, int code, const char *fmt, ...);
+void *dalloc(tm_context *c, size_t bytes);
+void dfree(tm_context *c, void *p);
+double now_s();
+
+#define TM_HIP(ctx, call)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return tmi::set_err((ctx), TM_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Slot engine
+// ---------------------------------------------------------------------------
+enum Kind { K_F64 = 0, K_MIXED = 1, K_LP16 = 2, K_LPBF = 3 };
+
+struct Job {
+    // input
+    bool noise = true;
+    uint64_t seed = 0, src = 0;
+    const double *b_canon = nullptr;  // explicit right-hand side (device, canonical)
+    double *x_canon = nullptr;        // explicit solution output (device, canonical)
+    double kappa = 0, a = 0;
+    double tol = 1e-10;
+    int max_iter = 100000;
+    int fixed = 0;
+    double delta = 0.1;
+    double *raw_out = nullptr;  // noise: device [9][T][16][2]
+    int want_true = 0;
+    // output
+    int status = 0;  // tm_status
+    int iters = 0, updates = 0;
+    double cg_rel = 0, true_rel = -1;
+    double t_fill = 0, t_done = 0;
+    // owner bookkeeping
+    void *owner = nullptr;
+    int owner_idx = 0;
+    bool hp = false;
+};
+
+struct Batch {
+    tm_context *ctx = nullptr;
+    const tm_gauge *G = nullptr;
+    Kind kind = K_F64;
+    int sp = tmk::P64, xr = tmk::P64;
+    int S = 1;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    size_t hsp = 0, hxr = 0, h64 = 0;
+    char *p = nullptr, *u = nullptr, *t = nullptr, *x = nullptr, *r = nullptr;
+    char *x64 = nullptr, *b64 = nullptr;
+    uint32_t *codes = nullptr;
+    char *FA = nullptr, *FB = nullptr, *FC = nullptr;  // FP64 full-field scratch [even | odd]
+    double *partial = nullptr;
+    int nblk = 0;
+    double *cpart = nullptr;
+    double *dres = nullptr;     // small device results
+    double *hres = nullptr;     // pinned mirror
+    tmk::SlotState *st = nullptr;
+    tmk::SlotState *st_h = nullptr;  // pinned
+    std::vector<Job *> slot_job;
+    std::vector<int> slot_updates;
+    std::vector<int> slot_pending_update;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int g_iters = 0;
+    bool in_flight = false;
+    int chunk = 8;
+    size_t bytes = 0;
+    double t_first = 0, t_last = 0;
+    long long iters_done = 0;
+};
+
+size_t batch_footprint(const tm_gauge *G, Kind kind, int S);
+int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk, hipStream_t stream, Batch **out);
+void batch_destroy(Batch *b);
+int batch_fill(Batch *b, int slot, Job *j);
+int batch_launch_chunk(Batch *b);
+// after the chunk's event completed: reliable updates and harvests; fills
+// *finished with the jobs that completed.  Returns tm_status.
+int batch_process(Batch *b, std::vector<Job *> &finished);
+int batch_active(const Batch *b);
+int batch_free_slot(const Batch *b);
+
+// Run queues of jobs on a set of batches until all are finished.
+int run_jobs(std::vector<Batch *> &batches, std::vector<std::vector<Job *>> &queues);
+
+Kind kind_of(const tm_solver_params &p);
+int kind_prec(Kind k);  // storage precision of the Dslash operands
+int auto_chunk(const tm_gauge *G, Kind k, int S);
+
+}  // namespace tmi

@@ -1,0 +1,83 @@
+// Host-side launchers of the libtm kernels (all asynchronous on a stream).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tm_types.h"
+
+namespace tmk {
+
+// Dslash with epilogue; sp = storage precision of in/in2/out/p (links of the
+// same precision), x/r in FP64 for sp = P64 else FP32.  Returns -1 on an
+// unsupported combination.
+int launch_dslash(int sp, bool dag, int epi, bool in2, const DslashArgs &A, hipStream_t s);
+
+// ---- CG scalars (one block per slot, fixed summation order) ----
+void launch_cg_alpha(SlotState *st, const double *partial, int nslot, int nblk, hipStream_t s);
+void launch_cg_beta(SlotState *st, const double *partial, int nslot, int nblk, hipStream_t s);
+// p = r + beta p for running slots (sp = p precision, xr = r precision)
+void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot,
+                     SlotState *st, int nslot, int swz, hipStream_t s);
+// start a slot: rr0 = sum(partial[0..nblk)), status RUNNING (or CONVERGED if rr0 == 0)
+void launch_slot_start(SlotState *st, const double *partial, int nblk, double kappa, double a, double tol2,
+                       int max_iter, double delta2, int mixed, hipStream_t s);
+// after an FP64 reliable update: rr_true = sum(partial); decide convergence, set beta
+void launch_reliable_finish(SlotState *st, const double *partial, int nblk, hipStream_t s);
+// out[k] = sum(partial[k*nblk .. (k+1)*nblk)) for k < n (fixed order)
+void launch_reduce(const double *partial, int nblk, int n, double *out, hipStream_t s);
+
+// ---- site-local vector kernels on nslot consecutive half fields ----
+void launch_convert(int pin, int pout, const Geom &g, const char *in, size_t in_slot, char *out, size_t out_slot,
+                    int nslot, hipStream_t s);
+void launch_zero(int p, const Geom &g, char *f, size_t slot, int nslot, hipStream_t s);
+// x64 += x32; x32 = 0
+void launch_accum_x(const Geom &g, char *x64, const char *x32_in, char *x32_zero, hipStream_t s);
+// per-block |f|^2 partials of one FP64 half field
+void launch_norm_partial(const Geom &g, const char *f, double *partial, hipStream_t s);
+// out = c * in with c per chirality: A^-1 (mode 1) or identity (mode 0), FP64
+void launch_site_diag(const Geom &g, int mode, double a, const char *in, char *out, hipStream_t s);
+
+// ---- noise ----
+// Z4 codes of both parities: codes[par*vh + cb]
+void launch_z4_codes(const Geom &g, uint64_t seed, uint64_t src, uint32_t *codes, hipStream_t s);
+// eta of one parity as an FP64 half field (times A^-1 when ainv != 0)
+void launch_z4_field(const Geom &g, const uint32_t *codes_par, int ainv, double a, char *out, hipStream_t s);
+// canonical FP64 layout [V][4][3][2]
+void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out, hipStream_t s);
+
+// ---- contractions ----
+int contract_nchunk(const Geom &g);
+// spin matrices of one source into raw_out [9][T][16][2] (FP64)
+void launch_contract(const Geom &g, const void *gauge64, const char *s_even, const char *s_odd,
+                     const uint32_t *codes, double *cpart, double *raw_out, hipStream_t s);
+// raw [n][9][T][16][2] -> ops [n][90][T][2]; gtab: [16][4] (col | phase << 2)
+void launch_project(int n, int lt, const double *raw, double *ops, const int *gtab_host, hipStream_t s);
+// TSM combination over per-source ops
+void launch_tsm_combine(int n_hp, int n_lp, int lt, const double *ops_hp, const double *ops_lp_corr,
+                        const double *ops_lp_bulk, double *est, double *var_re, double *var_im, hipStream_t s);
+
+// ---- layout ----
+// canonical FP64 gauge (device) -> per-precision link arrays
+void launch_gauge_pack(int p, const Geom &g, const double *canon, void *out, hipStream_t s);
+// canonical full-lattice spinors <-> layout (full field = even half, then odd half)
+void launch_field_import(int p, const Geom &g, int nrhs, const double *canon, char *field, hipStream_t s);
+void launch_field_export(int p, const Geom &g, int nrhs, const char *field, double *canon, hipStream_t s);
+
+// streaming copy probe
+void launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+// gamma table for the projection: [16][4] entries (column | phase << 2),
+// phase 0..3 = 1, i, -1, -i; built from the four basis matrices.
+const int *gamma_table();
+
+__host__ __device__ inline size_t half_bytes(int p, const Geom &g)
+{
+    return (size_t)g.vh * (p == P64 ? 192 : p == P32 ? 96 : 52);
+}
+inline size_t link_array_bytes(int p, const Geom &g)
+{
+    return (size_t)2 * 4 * g.vh * (p == P64 ? 96 : p == P32 ? 48 : 24);
+}
+__host__ __device__ inline int nblk_of(const Geom &g) { return (g.vh + BLOCK - 1) / BLOCK; }
+
+}  // namespace tmk

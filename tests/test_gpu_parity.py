@@ -1,0 +1,226 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_1401_6749_amd import inputs
+from tests import gpu_util as GU
+
+pytestmark = pytest.mark.gpu
+
+# lattices: smallest (neighbours alias), ragged (V/2 not a multiple of the
+# 256-thread block, timeslices not block aligned), a several-tile one
+DIMS_SET = [(2, 2, 2, 2), (6, 4, 2, 8), (4, 4, 4, 4), (8, 6, 4, 10)]
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8), (8, 8, 8, 16)])
+def test_z4_bit_exact(oracle, dims):
+    torch = GU.torch_mod()
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    V = int(np.prod(dims))
+    for seed, src in [(101, 0), (101, 15), (2**40 + 3, 123456), (0, 0)]:
+        out = torch.empty(V, 4, 3, 2, dtype=torch.float64, device="cuda")
+        tm.tm_z4_source(ctx, dims, seed, src, out)
+        torch.cuda.synchronize()
+        got = GU.from_dev(out).reshape(V, 4, 3)
+        want = oracle.z4_source(dims, seed, src)
+        assert np.array_equal(got.view(np.float64), want.view(np.float64)), (seed, src)
+
+
+@pytest.mark.parametrize("dims", DIMS_SET)
+@pytest.mark.parametrize("tbc", [-1, 1])
+def test_dslash_f64_all_ops(oracle, dims, tbc):
+    U = inputs.gauge_field(dims, seed=7)
+    g = GU.load(dims, U, tbc)
+    kappa, a = 0.1636, 0.0033
+    psi = np.stack([inputs.random_spinor(dims, 11), inputs.random_spinor(dims, 12)])
+    for op in ("hop", "m", "mdag", "mhat", "mhat_dag", "mhat_dag_mhat"):
+        got = GU.apply_op(g, op, kappa, a, "f64", psi, dims)
+        for r in range(2):
+            if op == "hop":
+                want = oracle.dhop(dims, tbc, U, psi[r])
+            elif op == "m":
+                want = oracle.apply_M(dims, tbc, U, kappa, a, psi[r])
+            elif op == "mdag":
+                want = oracle.apply_M(dims, tbc, U, kappa, a, psi[r], dag=True)
+            elif op == "mhat":
+                want = oracle.apply_mhat(dims, tbc, U, kappa, a, psi[r])
+            elif op == "mhat_dag":
+                want = oracle.apply_mhat(dims, tbc, U, kappa, a, psi[r], dag=True)
+            else:
+                want = oracle.apply_mhat(dims, tbc, U, kappa, a, oracle.apply_mhat(dims, tbc, U, kappa, a, psi[r]),
+                                         dag=True)
+            assert GU.relerr(got[r], want) < 1e-14, (op, r)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-6), ("f16", 3e-3), ("bf16", 2e-2)])
+def test_dslash_reduced_precision(oracle, prec, tol):
+    dims = (8, 6, 4, 10)
+    U = inputs.gauge_field(dims, seed=9)
+    g = GU.load(dims, U)
+    kappa, a = 0.1636, 0.01
+    psi = inputs.random_spinor(dims, 3)[None]
+    for op in ("hop", "m", "mhat_dag_mhat"):
+        got = GU.apply_op(g, op, kappa, a, prec, psi, dims)[0]
+        if op == "hop":
+            want = oracle.dhop(dims, -1, U, psi[0])
+        elif op == "m":
+            want = oracle.apply_M(dims, -1, U, kappa, a, psi[0])
+        else:
+            want = oracle.apply_mhat(dims, -1, U, kappa, a, oracle.apply_mhat(dims, -1, U, kappa, a, psi[0]), dag=True)
+        assert GU.relerr(got, want) < tol, (prec, op, GU.relerr(got, want))
+
+
+def test_dslash_multi_rhs_equals_single(oracle):
+    """A 12-RHS launch gives bitwise the same fields as 12 single launches."""
+    dims = (4, 4, 4, 8)
+    U = inputs.gauge_field(dims, seed=5)
+    g = GU.load(dims, U)
+    psi = np.stack([inputs.random_spinor(dims, 100 + r) for r in range(12)])
+    for prec in ("f64", "f32", "f16", "bf16"):
+        many = GU.apply_op(g, "mhat_dag_mhat", 0.12, 0.01, prec, psi, dims)
+        for r in (0, 5, 11):
+            one = GU.apply_op(g, "mhat_dag_mhat", 0.12, 0.01, prec, psi[r:r + 1], dims)[0]
+            assert np.array_equal(many[r], one), (prec, r)
+
+
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (6, 4, 2, 8)])
+def test_cg_f64_matched_iterations(oracle, dims):
+    """FP64 CG with the oracle's iteration count: same iterate up to rounding."""
+    torch = GU.torch_mod()
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    U = inputs.gauge_field(dims, seed=1)
+    g = GU.load(dims, U)
+    kappa, a = 0.12, 0.01
+    V = int(np.prod(dims))
+    etas = np.stack([oracle.z4_source(dims, 42, j) for j in range(3)])
+    b = GU.to_dev(etas)
+    x = torch.zeros_like(b)
+    for j in range(3):
+        s_or, it, rel, tr = oracle.solve(dims, -1, U, kappa, a, etas[j], tol=1e-10)
+        # tolerance-stopped solve: same iteration count and solution
+        p = tm.solver_params("f64", tol=1e-10)
+        rc, st = tm.tm_cg_solve(ctx, g, kappa, a, p, 1, b[j:j + 1], x[j:j + 1])
+        got = GU.from_dev(x[j]).reshape(V, 4, 3)
+        assert st[0]["iters"] == it
+        assert GU.relerr(got, s_or) < 1e-11
+        assert st[0]["true_rel_resid"] < 1e-9
+        # matched iterations
+        s8, it8, _, _ = oracle.solve(dims, -1, U, kappa, a, etas[j], fixed_iters=it // 2)
+        p8 = tm.solver_params("f64", fixed_iters=it // 2)
+        tm.tm_cg_solve(ctx, g, kappa, a, p8, 1, b[j:j + 1], x[j:j + 1])
+        assert GU.relerr(GU.from_dev(x[j]).reshape(V, 4, 3), s8) < 1e-12
+
+
+def test_cg_batched_equals_alone(oracle):
+    """Several right-hand sides in one multi-RHS solve give bitwise the same
+    solutions as each solved alone."""
+    torch = GU.torch_mod()
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 4, 4, 8)
+    U = inputs.gauge_field(dims, seed=2)
+    g = GU.load(dims, U)
+    etas = np.stack([oracle.z4_source(dims, 7, j) for j in range(5)])
+    b = GU.to_dev(etas)
+    for mode in ("f64", "lp", "mixed"):
+        p = tm.solver_params(mode, tol=1e-2 if mode == "lp" else 1e-10)
+        xb = torch.zeros_like(b)
+        tm.tm_cg_solve(ctx, g, 0.13, 0.01, p, 5, b, xb)
+        for j in (0, 3):
+            x1 = torch.zeros_like(b[j:j + 1])
+            tm.tm_cg_solve(ctx, g, 0.13, 0.01, p, 1, b[j:j + 1], x1)
+            assert torch.equal(x1[0], xb[j]), (mode, j)
+
+
+@pytest.mark.parametrize("mode,half", [("mixed", "f16"), ("lp", "f16"), ("lp", "bf16")])
+def test_cg_reduced_precision_residuals(oracle, mode, half):
+    torch = GU.torch_mod()
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (8, 6, 4, 10)
+    U = inputs.gauge_field(dims, seed=4)
+    g = GU.load(dims, U)
+    kappa, a = 0.12, 0.01
+    eta = oracle.z4_source(dims, 3, 0)
+    b = GU.to_dev(eta[None])
+    x = torch.zeros_like(b)
+    tol = 1e-10 if mode == "mixed" else 1e-2
+    p = tm.solver_params(mode, tol=tol, half=half)
+    rc, st = tm.tm_cg_solve(ctx, g, kappa, a, p, 1, b, x)
+    s_or, it, _, _ = oracle.solve(dims, -1, U, kappa, a, eta, tol=tol)
+    got = GU.from_dev(x[0]).reshape(-1, 4, 3)
+    if mode == "mixed":
+        assert st[0]["true_rel_resid"] < 1e-8
+        assert st[0]["reliable_updates"] >= 1
+        assert GU.relerr(got, s_or) < 1e-7
+    else:
+        assert st[0]["cg_rel_resid"] <= 1e-2
+        assert st[0]["true_rel_resid"] < 0.2
+        assert abs(st[0]["iters"] - it) <= max(3, it // 5)
+
+
+def test_loops_tsm_f64_parity(oracle):
+    """FP64 path, config-1 shaped: loops per source and the TSM estimate
+    match the oracle to 1e-10 relative."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 4, 4, 4)
+    U = inputs.gauge_field(dims, seed=1)
+    g = GU.load(dims, U)
+    kappa, a = 0.12, 0.01
+    n_hp, n_lp = 3, 5
+    P = tm.tsm_params(kappa, a, 101, n_hp, n_lp, hp=tm.solver_params("f64", tol=1e-10),
+                      lp=tm.solver_params("f64", tol=1e-2), batch=4, want_true_resid=1)
+    r = tm.tm_loops_tsm(ctx, g, P, dims[3], want_raw=True)
+    ref = oracle.loops_tsm(dims, -1, U, kappa, a, 101, n_hp, n_lp, hp_tol=1e-10, lp_tol=1e-2, return_raw=True)
+    for j in range(n_hp):
+        assert GU.relerr(r["raw_hp"][j], ref["hp_raw"][j]) < 1e-10
+    for j in range(n_hp + n_lp):
+        assert GU.relerr(r["raw_lp"][j], ref["lp_raw"][j]) < 1e-10
+    assert GU.relerr(r["est"], ref["est"]) < 1e-10
+    fin = np.isfinite(ref["var_re"])
+    assert np.allclose(r["var_re"][fin], ref["var_re"][fin], rtol=1e-8, atol=1e-14 * np.abs(ref["var_re"]).max())
+    st = r["stats"]
+    assert st["hp_solves"] == n_hp and st["lp_solves"] == n_hp + n_lp
+    assert st["max_hp_true_resid"] < 1e-9
+    # host projection utility agrees with the device projection
+    ops = tm.tm_project_loops(r["raw_lp"])
+    assert np.allclose(ops, np.array([oracle.project(P_) for P_ in r["raw_lp"]]), atol=1e-13)
+
+
+def test_device_projection_single_source(oracle):
+    """One source, no correction set: the estimate is that source's device
+    projection, compared with the oracle's projection of the same spin
+    matrices (isolates the projection kernel)."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 2, 2, 6)
+    U = inputs.gauge_field(dims, seed=3)
+    g = GU.load(dims, U)
+    P = tm.tsm_params(0.12, 0.02, 5, 0, 1, lp=tm.solver_params("f64", tol=1e-6), batch=1)
+    r = tm.tm_loops_tsm(ctx, g, P, dims[3], want_raw=True)
+    want = oracle.project(r["raw_lp"][0])
+    assert np.allclose(r["est"], want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+def test_loops_plain_estimator_c1(oracle):
+    """Config 1: 16 sources, FP64 to 1e-10, plain estimator (n_hp = 0)."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 4, 4, 4)
+    U = inputs.gauge_field(dims, seed=1)
+    g = GU.load(dims, U)
+    P = tm.tsm_params(0.12, 0.01, 101, 0, 16, lp=tm.solver_params("f64", tol=1e-10), batch=12)
+    r = tm.tm_loops_tsm(ctx, g, P, 4)
+    ref = oracle.loops_tsm(dims, -1, U, 0.12, 0.01, 101, 0, 16, lp_tol=1e-10)
+    assert GU.relerr(r["est"], ref["est"]) < 1e-10
+    assert np.allclose(r["var_re"], ref["var_re"], rtol=1e-7)
