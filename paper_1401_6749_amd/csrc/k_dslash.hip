@@ -129,7 +129,8 @@ __device__ __forceinline__ void coefs(int mode, double kappa, double a, cpx<T> P
     }
 }
 
-template <int SP, bool DAG, int EPI, bool IN2>
+// SLOT: per-slot solver state (CG chunks) or uniform parameters (operator calls)
+template <int SP, bool DAG, int EPI, bool IN2, bool SLOT>
 __global__ __launch_bounds__(BLOCK) void k_dslash(const DslashArgs A)
 {
     using T = typename Real<SP>::T;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(BLOCK) void k_dslash(const DslashArgs A)
     int sblk, slot;
     if (!map_block(A.nblk_site, A.nslot, A.swz, sblk, slot)) return;
     double kappa = A.kappa_u, a = A.a_u, alpha = 0;
-    if (A.st) {
+    if constexpr (SLOT) {
         const SlotState &st = A.st[slot];
         if (st.status != ST_RUNNING) return;
         kappa = st.kappa;
@@ -214,7 +215,10 @@ static void launch_t(const DslashArgs &A, hipStream_t s)
 {
     const int total = A.nblk_site * A.nslot;
     const int grid = A.swz ? 8 * ((total + 7) / 8) : total;
-    hipLaunchKernelGGL((k_dslash<SP, DAG, EPI, IN2>), dim3(grid), dim3(BLOCK), 0, s, A);
+    if (A.st)
+        hipLaunchKernelGGL((k_dslash<SP, DAG, EPI, IN2, true>), dim3(grid), dim3(BLOCK), 0, s, A);
+    else
+        hipLaunchKernelGGL((k_dslash<SP, DAG, EPI, IN2, false>), dim3(grid), dim3(BLOCK), 0, s, A);
 }
 
 template <int SP>
