@@ -11,6 +11,7 @@
 #include <cstring>
 #include <thread>
 
+#include "tm_arena.h"
 #include "tm_internal.h"
 
 using namespace tmk;
@@ -608,15 +609,26 @@ extern "C" int tm_loops_tsm(tm_context *ctx, const tm_gauge *G, const tm_tsm_par
     return tsm_run(ctx, G, P, est, var_re, var_im, raw, stats);
 }
 
-int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *vre, double *vim,
-            double *raw_host, tm_tsm_stats *stats)
+int tsm_check(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P)
 {
-    if (!G || !P || !est || !vre || !vim) return set_err(ctx, TM_ERR_ARG, "tm_loops_tsm: null argument");
+    if (!G || !P) return set_err(ctx, TM_ERR_ARG, "null gauge or parameters");
+    if (G->ctx != ctx) return set_err(ctx, TM_ERR_ARG, "gauge field belongs to another context");
     if (P->n_hp < 0 || P->n_lp < 0 || P->n_hp + P->n_lp < 1)
-        return set_err(ctx, TM_ERR_ARG, "tm_loops_tsm: need n_hp >= 0, n_lp >= 0 and at least one source");
+        return set_err(ctx, TM_ERR_ARG, "need n_hp >= 0, n_lp >= 0 and at least one source");
+    if (P->n_hp + P->n_lp > (1 << 24)) return set_err(ctx, TM_ERR_ARG, "too many sources");
+    if (P->batch < 0 || P->batch > MAX_SLOTS) return set_err(ctx, TM_ERR_ARG, "batch must be 0..%d", MAX_SLOTS);
     int rc = TM_OK;
     if (P->n_hp > 0 && (rc = check_solver(ctx, G, &P->hp))) return rc;
     if ((rc = check_solver(ctx, G, &P->lp))) return rc;
+    return TM_OK;
+}
+
+int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *vre, double *vim,
+            double *raw_host, tm_tsm_stats *stats)
+{
+    if (!est || !vre || !vim) return set_err(ctx, TM_ERR_ARG, "tm_loops_tsm: null output");
+    int rc = tsm_check(ctx, G, P);
+    if (rc) return rc;
     const int batch = P->batch > 0 ? std::min(P->batch, MAX_SLOTS) : 12;
     TM_HIP(ctx, hipSetDevice(ctx->device));
     const double t0 = now_s();
@@ -769,5 +781,33 @@ extern "C" int tm_selftest(void)
     int dims[4] = {6, 4, 2, 8};
     Geom g = make_geom(dims, -1);
     if (g.vh != 6 * 4 * 2 * 8 / 2 || g.v3h * dims[3] != g.vh || g.st != g.v3h) return 3;
+    // arena: random allocations and releases keep blocks disjoint, in range,
+    // aligned, and coalesce back to one free block
+    {
+        tmi::Arena A;
+        char *base = (char *)(uintptr_t)0x10000000;
+        const size_t size = 1 << 24;
+        A.init(base, size);
+        std::vector<std::pair<char *, size_t>> live;
+        uint64_t z = 12345;
+        for (int it = 0; it < 20000; it++) {
+            z = z * 6364136223846793005ull + 1442695040888963407ull;
+            if ((z >> 33) % 3 && live.size() < 200) {
+                size_t n = 1 + (z >> 40) % 300000;
+                char *p = (char *)A.alloc(n);
+                if (!p) continue;
+                if ((size_t)(p - base) % 256 || p < base || p + n > base + size) return 4;
+                for (auto &q : live)
+                    if (p < q.first + q.second && q.first < p + n) return 5;
+                live.push_back({p, n});
+            } else if (!live.empty()) {
+                size_t k = (z >> 20) % live.size();
+                A.release(live[k].first);
+                live.erase(live.begin() + k);
+            }
+        }
+        for (auto &q : live) A.release(q.first);
+        if (A.used != 0 || A.largest_free() != size || A.free_.size() != 1) return 6;
+    }
     return 0;
 }

@@ -73,7 +73,8 @@ static char *carve(char *&cur, size_t bytes)
     return p;
 }
 
-int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk, hipStream_t stream, Batch **out)
+int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk, hipStream_t stream, Batch **out,
+                 const Mem *mem)
 {
     if (S < 1 || S > MAX_SLOTS) return set_err(ctx, TM_ERR_ARG, "batch size %d outside 1..%d", S, MAX_SLOTS);
     const int sp = kind_prec(kind);
@@ -92,7 +93,8 @@ int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk
     b->h64 = half_bytes(P64, g);
     b->nblk = nblk_of(g);
     b->bytes = batch_footprint(G, kind, S) + 32 * 256;
-    char *base = (char *)dalloc(ctx, b->bytes);
+    if (mem) b->mem = *mem;
+    char *base = (char *)(b->mem.alloc ? b->mem.alloc(b->mem.self, b->bytes) : dalloc(ctx, b->bytes));
     if (!base) {
         delete b;
         return set_err(ctx, TM_ERR_NOMEM, "cannot allocate %zu bytes of solver workspace", (size_t)batch_footprint(G, kind, S));
@@ -153,7 +155,12 @@ void batch_destroy(Batch *b)
     if (b->ev) (void)hipEventDestroy(b->ev);
     if (b->st_h) (void)hipHostFree(b->st_h);
     if (b->hres) (void)hipHostFree(b->hres);
-    if (b->p) dfree(b->ctx, b->p);
+    if (b->p) {
+        if (b->mem.free)
+            b->mem.free(b->mem.self, b->p);
+        else
+            dfree(b->ctx, b->p);
+    }
     delete b;
 }
 

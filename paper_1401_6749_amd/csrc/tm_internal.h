@@ -59,6 +59,14 @@ double now_s();
 // ---------------------------------------------------------------------------
 enum Kind { K_F64 = 0, K_MIXED = 1, K_LP16 = 2, K_LPBF = 3 };
 
+// Device memory source of a batch: the context allocator by default, or a
+// serving engine's arena.
+struct Mem {
+    void *(*alloc)(void *self, size_t bytes) = nullptr;
+    void (*free)(void *self, void *p) = nullptr;
+    void *self = nullptr;
+};
+
 struct Job {
     // input
     bool noise = true;
@@ -85,6 +93,7 @@ struct Job {
 
 struct Batch {
     tm_context *ctx = nullptr;
+    Mem mem;
     const tm_gauge *G = nullptr;
     Kind kind = K_F64;
     int sp = tmk::P64, xr = tmk::P64;
@@ -117,7 +126,8 @@ struct Batch {
 };
 
 size_t batch_footprint(const tm_gauge *G, Kind kind, int S);
-int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk, hipStream_t stream, Batch **out);
+int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk, hipStream_t stream, Batch **out,
+                 const Mem *mem = nullptr);
 void batch_destroy(Batch *b);
 int batch_fill(Batch *b, int slot, Job *j);
 int batch_launch_chunk(Batch *b);
