@@ -58,7 +58,7 @@ def test_create_without_gpu_fails_cleanly():
     from paper_1401_6749_amd import tm
 
     with pytest.raises(tm.TMError) as e:
-        tm.tm_create(0)
+        tm.tm_create(0, torch_allocator=False)
     assert e.value.code == tm.TM_ERR_ARG
 
 
