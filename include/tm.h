@@ -160,6 +160,13 @@ int tm_field_export(tm_context *ctx, const tm_gauge *gauge, tm_prec prec, int nr
 int tm_dslash(tm_context *ctx, const tm_gauge *gauge, tm_op op, double kappa, double two_kappa_mu,
               tm_prec prec, int nrhs, const void *in, void *out, void *hip_stream);
 
+/* As tm_dslash with explicit byte strides between consecutive fields of in
+ * and of out (multiples of 16, at least one field); same semantics and
+ * errors otherwise.  Lets callers lay batches out with padding. */
+int tm_dslash_ex(tm_context *ctx, const tm_gauge *gauge, tm_op op, double kappa, double two_kappa_mu,
+                 tm_prec prec, int nrhs, const void *in, size_t in_stride, void *out, size_t out_stride,
+                 void *hip_stream);
+
 /* ------------------------------------------------------------------ */
 /* Solver (Sec. 2.1: "the inverter, a CG solver")                       */
 /* ------------------------------------------------------------------ */

@@ -365,8 +365,24 @@ static bool overlap(const void *a, size_t na, const void *b, size_t nb)
     return x < y + nb && y < x + na;
 }
 
+extern "C" int tm_dslash_ex(tm_context *ctx, const tm_gauge *G, tm_op op, double kappa, double a, tm_prec prec,
+                            int nrhs, const void *in, size_t in_stride, void *out, size_t out_stride,
+                            void *hip_stream);
+
 extern "C" int tm_dslash(tm_context *ctx, const tm_gauge *G, tm_op op, double kappa, double a, tm_prec prec,
                          int nrhs, const void *in, void *out, void *hip_stream)
+{
+    const int p = prec_index(prec);
+    if (!ctx) return TM_ERR_ARG;
+    if (!G || p < 0) return set_err(ctx, TM_ERR_ARG, "tm_dslash: bad gauge or precision");
+    const bool full = op == TM_OP_HOP || op == TM_OP_M || op == TM_OP_MDAG;
+    const size_t fb = half_bytes(p, G->g) * (full ? 2 : 1);
+    return tm_dslash_ex(ctx, G, op, kappa, a, prec, nrhs, in, fb, out, fb, hip_stream);
+}
+
+extern "C" int tm_dslash_ex(tm_context *ctx, const tm_gauge *G, tm_op op, double kappa, double a, tm_prec prec,
+                            int nrhs, const void *in, size_t in_stride, void *out, size_t out_stride,
+                            void *hip_stream)
 {
     if (!ctx) return TM_ERR_ARG;
     const int p = prec_index(prec);
@@ -379,18 +395,21 @@ extern "C" int tm_dslash(tm_context *ctx, const tm_gauge *G, tm_op op, double ka
     const size_t hb = half_bytes(p, g);
     const bool full = op == TM_OP_HOP || op == TM_OP_M || op == TM_OP_MDAG;
     const size_t fb = full ? 2 * hb : hb;
-    if (overlap(in, fb * nrhs, out, fb * nrhs)) return set_err(ctx, TM_ERR_ARG, "tm_dslash: in and out overlap");
+    if (in_stride < fb || out_stride < fb || in_stride % 16 || out_stride % 16)
+        return set_err(ctx, TM_ERR_ARG, "tm_dslash: strides must be multiples of 16 and at least one field");
+    if (overlap(in, in_stride * (nrhs - 1) + fb, out, out_stride * (nrhs - 1) + fb))
+        return set_err(ctx, TM_ERR_ARG, "tm_dslash: in and out overlap");
     hipStream_t s = (hipStream_t)hip_stream;
     DslashArgs A;
     std::memset(&A, 0, sizeof(A));
     A.g = g;
     A.gauge = G->links[p];
     A.nslot = nrhs;
-    A.nblk_site = nblk_of(g);
     A.swz = ctx->swz;
     A.kappa_u = kappa;
     A.a_u = a;
-    A.in_slot = A.in2_slot = A.out_slot = fb;
+    A.in_slot = A.in2_slot = in_stride;
+    A.out_slot = out_stride;
     const char *ic = (const char *)in;
     char *oc = (char *)out;
     if (full) {
@@ -399,6 +418,7 @@ extern "C" int tm_dslash(tm_context *ctx, const tm_gauge *G, tm_op op, double ka
         const bool in2 = op != TM_OP_HOP;
         for (int par = 0; par < 2; par++) {
             A.in = ic + (1 - par) * hb;
+            A.in2_slot = in_stride;
             A.in2 = in2 ? ic + par * hb : nullptr;
             A.out = oc + par * hb;
             A.out_par = par;
@@ -416,8 +436,8 @@ extern "C" int tm_dslash(tm_context *ctx, const tm_gauge *G, tm_op op, double ka
             if (!ctx->op_tmp) return set_err(ctx, TM_ERR_NOMEM, "tm_dslash: no memory for temporaries");
         }
         char *t = (char *)ctx->op_tmp, *u = t + hb * nrhs;
-        auto mhat = [&](const char *src, char *dst, bool dag) {
-            A.in_slot = fb;
+        auto mhat = [&](const char *src, size_t src_stride, char *dst, size_t dst_stride, bool dag) {
+            A.in_slot = src_stride;
             A.out_slot = hb;
             A.in = src;
             A.in2 = nullptr;
@@ -426,8 +446,8 @@ extern "C" int tm_dslash(tm_context *ctx, const tm_gauge *G, tm_op op, double ka
             A.coef = dag ? CM_AINV_DAG : CM_AINV;
             launch_dslash(p, dag, EPI_PLAIN, false, A, s);
             A.in_slot = hb;
-            A.in2_slot = fb;
-            A.out_slot = fb;
+            A.in2_slot = src_stride;
+            A.out_slot = dst_stride;
             A.in = t;
             A.in2 = src;
             A.out = dst;
@@ -435,11 +455,11 @@ extern "C" int tm_dslash(tm_context *ctx, const tm_gauge *G, tm_op op, double ka
             A.coef = dag ? CM_MHAT_DAG : CM_MHAT;
             launch_dslash(p, dag, EPI_PLAIN, true, A, s);
         };
-        if (op == TM_OP_MHAT) mhat(ic, oc, false);
-        else if (op == TM_OP_MHAT_DAG) mhat(ic, oc, true);
+        if (op == TM_OP_MHAT) mhat(ic, in_stride, oc, out_stride, false);
+        else if (op == TM_OP_MHAT_DAG) mhat(ic, in_stride, oc, out_stride, true);
         else {
-            mhat(ic, u, false);
-            mhat(u, oc, true);
+            mhat(ic, in_stride, u, hb, false);
+            mhat(u, hb, oc, out_stride, true);
         }
     }
     TM_HIP(ctx, hipGetLastError());
@@ -459,6 +479,8 @@ static int check_solver(tm_context *ctx, const tm_gauge *G, const tm_solver_para
     if (p->fixed_iters <= 0 && p->max_iter < 1) return set_err(ctx, TM_ERR_ARG, "max_iter must be >= 1");
     const int sp = kind_prec(kind_of(*p));
     if (!(G->precs & (1u << sp))) return set_err(ctx, TM_ERR_ARG, "gauge field not loaded in the solver's precision");
+    if (p->mode == TM_SOLVE_LP && !(G->precs & (1u << P32)))
+        return set_err(ctx, TM_ERR_ARG, "LP solves also need the FP32 links");
     return TM_OK;
 }
 

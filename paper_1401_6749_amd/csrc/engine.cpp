@@ -39,17 +39,22 @@ int kind_prec(Kind k)
 
 static int kind_xr(Kind k) { return k == K_F64 ? P64 : P32; }
 
+// Pitch between the slots of a multi-slot field: the field plus 17 x 256
+// bytes, so the same site of consecutive slots (at power-of-two-sized
+// distances otherwise) does not land on one memory channel.
+static size_t slot_pitch(size_t field) { return ((field + 255) & ~(size_t)255) + 17 * 256; }
+
 size_t batch_footprint(const tm_gauge *G, Kind kind, int S)
 {
     const Geom &g = G->g;
     const int sp = kind_prec(kind), xr = kind_xr(kind);
     size_t b = 0;
-    b += (size_t)S * 3 * half_bytes(sp, g);            // p, u, t
-    b += (size_t)S * 2 * half_bytes(xr, g);            // x, r
+    b += (size_t)S * 3 * slot_pitch(half_bytes(sp, g));  // p, u, t
+    b += (size_t)S * 2 * slot_pitch(half_bytes(xr, g));  // x, r
     if (kind == K_MIXED) b += (size_t)S * 2 * half_bytes(P64, g);  // x64, b64
     b += (size_t)S * 2 * g.vh * sizeof(uint32_t);      // noise codes
     b += 3 * 2 * half_bytes(P64, g);                   // FP64 scratch FA, FB, FC
-    b += (size_t)S * nblk_of(g) * sizeof(double) + 4096;
+    b += (size_t)S * ntile_of(g) * sizeof(double) + 4096;
     b += (size_t)g.L[3] * contract_nchunk(g) * 288 * sizeof(double);
     b += (size_t)S * sizeof(SlotState) + 64 * sizeof(double) + 16 * 256;
     return b;
@@ -80,6 +85,8 @@ int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk
     const int sp = kind_prec(kind);
     if (!(G->precs & (1u << sp)))
         return set_err(ctx, TM_ERR_ARG, "gauge field was not loaded in the precision this solver needs");
+    if ((kind == K_LP16 || kind == K_LPBF) && !(G->precs & (1u << P32)))
+        return set_err(ctx, TM_ERR_ARG, "low-precision solves also need the FP32 links (preparation)");
     Batch *b = new Batch();
     b->ctx = ctx;
     b->G = G;
@@ -88,10 +95,10 @@ int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk
     b->xr = kind_xr(kind);
     b->S = S;
     const Geom &g = G->g;
-    b->hsp = half_bytes(sp, g);
-    b->hxr = half_bytes(b->xr, g);
+    b->hsp = slot_pitch(half_bytes(sp, g));
+    b->hxr = slot_pitch(half_bytes(b->xr, g));
     b->h64 = half_bytes(P64, g);
-    b->nblk = nblk_of(g);
+    b->nblk = ntile_of(g);  // per-slot partial sums (64-site tiles)
     b->bytes = batch_footprint(G, kind, S) + 32 * 256;
     if (mem) b->mem = *mem;
     char *base = (char *)(b->mem.alloc ? b->mem.alloc(b->mem.self, b->bytes) : dalloc(ctx, b->bytes));
@@ -188,7 +195,6 @@ static DslashArgs dargs(const Batch *b, int sp)
     A.g = b->G->g;
     A.gauge = b->G->links[sp];
     A.nslot = 1;
-    A.nblk_site = b->nblk;
     A.swz = b->ctx->swz;
     return A;
 }
@@ -223,6 +229,44 @@ static void load_eta(Batch *b, int slot, Job *j)
     }
 }
 
+// Prep/reconstruction precision of a job: LP noise solves run them in FP32
+// (their target is a 1e-2 residual), everything else in FP64.
+static int prep_prec(const Batch *b, const Job *j)
+{
+    return (j->noise && !j->want_true && (b->kind == K_LP16 || b->kind == K_LPBF)) ? P32 : P64;
+}
+
+// Dslash with uniform (kappa, a) in precision pp on single fields
+static void dsl(const Batch *b, int pp, bool dag, int epi, int coef, int out_par, const char *in, const char *in2,
+                char *out, double kappa, double a, double *partial = nullptr)
+{
+    DslashArgs A = dargs(b, pp);
+    A.in = in;
+    A.in2 = in2;
+    A.out = out;
+    A.out_par = out_par;
+    A.coef = coef;
+    A.kappa_u = kappa;
+    A.a_u = a;
+    A.partial = partial;
+    launch_dslash(pp, dag, epi, in2 != nullptr, A, b->stream);
+}
+
+// Dslash whose noise input comes from the slot's Z4 codes (src 3: prep, src 2: reconstruction)
+static void dsl_codes(const Batch *b, int pp, int src, int coef, int out_par, int slot, const char *in, char *out,
+                      double kappa, double a)
+{
+    DslashArgs A = dargs(b, pp);
+    A.codes = b->codes + (size_t)slot * 2 * b->G->g.vh;
+    A.in = in;
+    A.out = out;
+    A.out_par = out_par;
+    A.coef = coef;
+    A.kappa_u = kappa;
+    A.a_u = a;
+    launch_dslash_codes(pp, src, A, b->stream);
+}
+
 int batch_fill(Batch *b, int slot, Job *j)
 {
     const Geom &g = b->G->g;
@@ -232,7 +276,40 @@ int batch_fill(Batch *b, int slot, Job *j)
     b->slot_pending_update[slot] = 0;
     j->t_fill = now_s();
     if (b->t_first == 0) b->t_first = j->t_fill;
-    if (j->noise) launch_z4_codes(g, j->seed, j->src, b->codes + (size_t)slot * 2 * g.vh, s);
+    const bool mixed = b->kind == K_MIXED;
+    const double tol2 = j->fixed > 0 ? 0.0 : j->tol * j->tol;
+    const int maxit = j->fixed > 0 ? j->fixed : j->max_iter;
+    const double delta = j->delta > 0 ? j->delta : 0.1;
+    double *part = b->partial + (size_t)slot * b->nblk;
+    const int pp = prep_prec(b, j);
+    if (j->noise) {
+        // bhat_e = eta_e + kappa D_eo A^-1 eta_o straight from the Z4 codes,
+        // rhs = Mhat^dag bhat = A^dag bhat - kappa^2 D'_eo A^-dag D'_oe bhat
+        launch_z4_codes(g, j->seed, j->src, b->codes + (size_t)slot * 2 * g.vh, s);
+        char *Be = b->FB, *To = b->FC;  // scratch fields in precision pp
+        dsl_codes(b, pp, 3, CM_PREP, 0, slot, nullptr, Be, j->kappa, j->a);
+        dsl(b, pp, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, nullptr, To, j->kappa, j->a);
+        if (pp == P32) {
+            // LP: the right-hand side lands directly in r (FP32)
+            char *r = b->r + slot * b->hxr;
+            dsl(b, P32, true, EPI_NORM, CM_MHAT_DAG, 0, To, Be, r, j->kappa, j->a, part);
+            launch_slot_start(b->st + slot, part, b->nblk, j->kappa, j->a, tol2, maxit, delta * delta, 0, s);
+            launch_convert(P32, b->sp, g, r, 0, b->p + slot * b->hsp, 0, 1, s);
+            launch_zero(P32, g, b->x + slot * b->hxr, 0, 1, s);
+            return TM_OK;
+        }
+        char *Ce = b->FA;
+        dsl(b, P64, true, EPI_NORM, CM_MHAT_DAG, 0, To, Be, Ce, j->kappa, j->a, part);
+        launch_slot_start(b->st + slot, part, b->nblk, j->kappa, j->a, tol2, maxit, delta * delta, mixed ? 1 : 0, s);
+        launch_convert(P64, b->xr, g, Ce, 0, b->r + slot * b->hxr, 0, 1, s);
+        launch_convert(P64, b->sp, g, Ce, 0, b->p + slot * b->hsp, 0, 1, s);
+        launch_zero(b->xr, g, b->x + slot * b->hxr, 0, 1, s);
+        if (mixed) {
+            launch_convert(P64, P64, g, Ce, 0, b->b64 + slot * b->h64, 0, 1, s);
+            launch_zero(P64, g, b->x64 + slot * b->h64, 0, 1, s);
+        }
+        return TM_OK;
+    }
     load_eta(b, slot, j);
     char *Ee = b->FA, *Eo = b->FA + b->h64;
     char *Be = b->FB, *Bo = b->FB + b->h64;
@@ -242,12 +319,7 @@ int batch_fill(Batch *b, int slot, Job *j)
     d64(b, false, EPI_PLAIN, CM_PREP, 0, Bo, Ee, Be, j->kappa, j->a);
     // rhs = Mhat^dag bhat = A^dag bhat - kappa^2 D'_eo A^-dag D'_oe bhat
     d64(b, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, nullptr, Bo, j->kappa, j->a);
-    double *part = b->partial + (size_t)slot * b->nblk;
     d64(b, true, EPI_NORM, CM_MHAT_DAG, 0, Bo, Be, Ce, j->kappa, j->a, part);
-    const bool mixed = b->kind == K_MIXED;
-    const double tol2 = j->fixed > 0 ? 0.0 : j->tol * j->tol;
-    const int maxit = j->fixed > 0 ? j->fixed : j->max_iter;
-    const double delta = j->delta > 0 ? j->delta : 0.1;
     launch_slot_start(b->st + slot, part, b->nblk, j->kappa, j->a, tol2, maxit, delta * delta, mixed ? 1 : 0, s);
     launch_convert(P64, b->xr, g, Ce, 0, b->r + slot * b->hxr, 0, 1, s);
     launch_convert(P64, b->sp, g, Ce, 0, b->p + slot * b->hsp, 0, 1, s);
@@ -374,11 +446,48 @@ static void reliable_update(Batch *b, int slot)
     b->slot_updates[slot]++;
 }
 
-// reconstruct s = (s_e, s_o) in FP64, contract or export, optional true residual
+static void harvest64(Batch *b, int slot, const SlotState &S, Job *j);
+static int true_residual(Batch *b, int slot, Job *j);
+
+// reconstruct s = (s_e, s_o), contract or export, optional true residual
 static int harvest(Batch *b, int slot, const SlotState &S)
 {
     const Geom &g = b->G->g;
     Job *j = b->slot_job[slot];
+    hipStream_t s = b->stream;
+    if (prep_prec(b, j) == P32) {
+        // LP noise solve: s_e = x (FP32), s_o = A^-1 (eta_o + kappa D_oe s_e) from the codes,
+        // contraction on FP32 s with FP64 accumulation
+        const char *se32 = b->x + slot * b->hxr;
+        char *so32 = b->FC;
+        dsl_codes(b, P32, 2, CM_RECON, 1, slot, se32, so32, j->kappa, j->a);
+        if (j->raw_out)
+            launch_contract(P32, g, b->G->links[P64], se32, so32, b->codes + (size_t)slot * 2 * g.vh, b->cpart,
+                            j->raw_out, s);
+    } else {
+        harvest64(b, slot, S, j);
+    }
+    j->iters = S.iter;
+    j->updates = b->slot_updates[slot];
+    j->cg_rel = S.rr0 > 0 ? std::sqrt(std::max(S.status == ST_CONVERGED || S.status == ST_MAXITER ? S.rr : S.rr_new, 0.0) / S.rr0) : 0.0;
+    j->status = S.status == ST_CONVERGED ? TM_OK
+                : S.status == ST_MAXITER ? (j->fixed > 0 ? TM_OK : TM_ERR_NOCONV)
+                                         : TM_ERR_NUMERIC;
+    if (j->want_true) {
+        int e = true_residual(b, slot, j);
+        if (e != TM_OK) return e;
+    }
+    b->iters_done += S.iter;
+    j->t_done = now_s();
+    b->t_last = j->t_done;
+    b->slot_job[slot] = nullptr;
+    return TM_OK;
+}
+
+// FP64 reconstruction and contraction / export
+static void harvest64(Batch *b, int slot, const SlotState &S, Job *j)
+{
+    const Geom &g = b->G->g;
     hipStream_t s = b->stream;
     // s_e (FP64) into FC even half
     char *se = b->FC, *so = b->FC + b->h64;
@@ -391,44 +500,43 @@ static int harvest(Batch *b, int slot, const SlotState &S)
     } else {
         launch_convert(P32, P64, g, b->x + slot * b->hxr, 0, se, 0, 1, s);
     }
-    load_eta(b, slot, j);
-    char *Ee = b->FA, *Eo = b->FA + b->h64;
-    // s_o = A^-1 (eta_o + kappa D_oe s_e)
-    d64(b, false, EPI_PLAIN, CM_RECON, 1, se, Eo, so, j->kappa, j->a);
+    char *Eo = b->FA + b->h64;
     if (j->noise) {
+        // s_o = A^-1 (eta_o + kappa D_oe s_e) with eta_o from the codes
+        dsl_codes(b, P64, 2, CM_RECON, 1, slot, se, so, j->kappa, j->a);
         if (j->raw_out)
-            launch_contract(g, b->G->links[P64], se, so, b->codes + (size_t)slot * 2 * g.vh, b->cpart, j->raw_out, s);
+            launch_contract(P64, g, b->G->links[P64], se, so, b->codes + (size_t)slot * 2 * g.vh, b->cpart,
+                            j->raw_out, s);
     } else {
+        load_eta(b, slot, j);
+        d64(b, false, EPI_PLAIN, CM_RECON, 1, se, Eo, so, j->kappa, j->a);
         launch_field_export(P64, g, 1, b->FC, j->x_canon, s);
     }
-    j->iters = S.iter;
-    j->updates = b->slot_updates[slot];
-    j->cg_rel = S.rr0 > 0 ? std::sqrt(std::max(S.status == ST_CONVERGED || S.status == ST_MAXITER ? S.rr : S.rr_new, 0.0) / S.rr0) : 0.0;
-    j->status = S.status == ST_CONVERGED ? TM_OK
-                : S.status == ST_MAXITER ? (j->fixed > 0 ? TM_OK : TM_ERR_NOCONV)
-                                         : TM_ERR_NUMERIC;
-    if (j->want_true) {
-        // r = eta - M s on both parities, |r|^2 and |eta|^2
-        char *Be = b->FB, *Bo = b->FB + b->h64;
-        double *p0 = b->partial + (size_t)slot * b->nblk;
-        // even: eta_e - (A s_e - kappa D_eo s_o); odd: eta_o - (A s_o - kappa D_oe s_e)
-        d64(b, false, EPI_RESID, CM_M, 0, so, se, Be, j->kappa, j->a, p0, Ee);
-        launch_reduce(p0, b->nblk, 1, b->dres + 0, s);
-        d64(b, false, EPI_RESID, CM_M, 1, se, so, Bo, j->kappa, j->a, p0, Eo);
-        launch_reduce(p0, b->nblk, 1, b->dres + 1, s);
-        launch_norm_partial(g, Ee, p0, s);
-        launch_reduce(p0, b->nblk, 1, b->dres + 2, s);
-        launch_norm_partial(g, Eo, p0, s);
-        launch_reduce(p0, b->nblk, 1, b->dres + 3, s);
-        TM_HIP(b->ctx, hipMemcpyAsync(b->hres, b->dres, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-        TM_HIP(b->ctx, hipStreamSynchronize(s));
-        const double num = b->hres[0] + b->hres[1], den = b->hres[2] + b->hres[3];
-        j->true_rel = den > 0 ? std::sqrt(num / den) : 0.0;
-    }
-    b->iters_done += S.iter;
-    j->t_done = now_s();
-    b->t_last = j->t_done;
-    b->slot_job[slot] = nullptr;
+}
+
+// |eta - M s| / |eta| in FP64 (s in FC, eta rebuilt in FA)
+static int true_residual(Batch *b, int slot, Job *j)
+{
+    const Geom &g = b->G->g;
+    hipStream_t s = b->stream;
+    char *se = b->FC, *so = b->FC + b->h64;
+    load_eta(b, slot, j);
+    char *Ee = b->FA, *Eo = b->FA + b->h64;
+    char *Be = b->FB, *Bo = b->FB + b->h64;
+    double *p0 = b->partial + (size_t)slot * b->nblk;
+    // even: eta_e - (A s_e - kappa D_eo s_o); odd: eta_o - (A s_o - kappa D_oe s_e)
+    d64(b, false, EPI_RESID, CM_M, 0, so, se, Be, j->kappa, j->a, p0, Ee);
+    launch_reduce(p0, b->nblk, 1, b->dres + 0, s);
+    d64(b, false, EPI_RESID, CM_M, 1, se, so, Bo, j->kappa, j->a, p0, Eo);
+    launch_reduce(p0, b->nblk, 1, b->dres + 1, s);
+    launch_norm_partial(g, Ee, p0, s);
+    launch_reduce(p0, b->nblk, 1, b->dres + 2, s);
+    launch_norm_partial(g, Eo, p0, s);
+    launch_reduce(p0, b->nblk, 1, b->dres + 3, s);
+    TM_HIP(b->ctx, hipMemcpyAsync(b->hres, b->dres, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    TM_HIP(b->ctx, hipStreamSynchronize(s));
+    const double num = b->hres[0] + b->hres[1], den = b->hres[2] + b->hres[3];
+    j->true_rel = den > 0 ? std::sqrt(num / den) : 0.0;
     return TM_OK;
 }
 

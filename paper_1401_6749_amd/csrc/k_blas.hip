@@ -272,9 +272,9 @@ void launch_accum_x(const Geom &g, char *x64, const char *x32_in, char *x32_zero
     hipLaunchKernelGGL(k_accum_x, dim3(nblk_of(g)), dim3(BLOCK), 0, s, g, x64, x32_in, x32_zero);
 }
 
+// per-tile |f|^2 of one FP64 half field: partial[tile], 64-site tiles
 __global__ __launch_bounds__(BLOCK) void k_norm_partial(Geom g, const char *f, double *partial)
 {
-    __shared__ double lds[BLOCK / 64];
     const int cb = blockIdx.x * BLOCK + threadIdx.x;
     double part = 0.0;
     if (cb < g.vh) {
@@ -283,8 +283,9 @@ __global__ __launch_bounds__(BLOCK) void k_norm_partial(Geom g, const char *f, d
 #pragma unroll
         for (int k = 0; k < 12; k++) part += norm2(v[k]);
     }
-    part = block_sum<BLOCK>(part, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = part;
+    part = wave_sum(part);
+    const int tile = cb / TILE;
+    if ((threadIdx.x & 63) == 0 && tile < ntile_of(g)) partial[tile] = part;
 }
 
 void launch_norm_partial(const Geom &g, const char *f, double *partial, hipStream_t s)

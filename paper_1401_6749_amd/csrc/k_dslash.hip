@@ -12,31 +12,20 @@
 #include "tm_dev.h"
 #include "tm_launch.h"
 
-namespace tmk {
+#include <algorithm>
+#include <cstdlib>
 
-// Half-spinor projection for (1 + S g_mu) in the chiral basis.
-// psi[3*spin + colour]; h[0..2] = row 0, h[3..5] = row 1.
-template <class T, int MU, int S>
-__device__ __forceinline__ void project(const cpx<T> psi[12], cpx<T> h[6])
-{
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        const cpx<T> p0 = psi[c], p1 = psi[3 + c], p2 = psi[6 + c], p3 = psi[9 + c];
-        if (MU == 0) {  // rows: p0 - iS p3, p1 - iS p2
-            h[c] = S > 0 ? p0 - ti(p3) : p0 + ti(p3);
-            h[3 + c] = S > 0 ? p1 - ti(p2) : p1 + ti(p2);
-        } else if (MU == 1) {  // p0 - S p3, p1 + S p2
-            h[c] = S > 0 ? p0 - p3 : p0 + p3;
-            h[3 + c] = S > 0 ? p1 + p2 : p1 - p2;
-        } else if (MU == 2) {  // p0 - iS p2, p1 + iS p3
-            h[c] = S > 0 ? p0 - ti(p2) : p0 + ti(p2);
-            h[3 + c] = S > 0 ? p1 + ti(p3) : p1 - ti(p3);
-        } else {  // p0 + S p2, p1 + S p3
-            h[c] = S > 0 ? p0 + p2 : p0 - p2;
-            h[3 + c] = S > 0 ? p1 + p3 : p1 - p3;
-        }
-    }
-}
+#ifndef TM_DSLASH_WAVES_F64
+#define TM_DSLASH_WAVES_F64 2
+#endif
+#ifndef TM_DSLASH_WAVES_F32
+#define TM_DSLASH_WAVES_F32 3
+#endif
+#ifndef TM_DSLASH_WAVES_F16
+#define TM_DSLASH_WAVES_F16 4
+#endif
+
+namespace tmk {
 
 // Rebuild the four spin rows of (1 + S g_mu) psi from the transported half
 // spinor w and add them to acc.
@@ -64,41 +53,246 @@ __device__ __forceinline__ void accum(cpx<T> acc[12], const cpx<T> w[6])
     }
 }
 
-template <class T, int SP, int MU, bool DAG>
-__device__ __forceinline__ void hop_mu(const DslashArgs &A, const Site &s, const char *in, cpx<T> acc[12])
+// Buffer loads: one uniform resource per field (SGPRs), the component-group
+// stride in the scalar offset and a single 32-bit lane offset per neighbour,
+// so the eight neighbours do not each hold seven 64-bit lane addresses.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t mkrsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ u32x4 bld16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ u32x2 bld8(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ uint32_t bld4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ double2 as_d2(u32x4 v)
+{
+    double2 d;
+    __builtin_memcpy(&d, &v, 16);
+    return d;
+}
+__device__ __forceinline__ float4 as_f4(u32x4 v)
+{
+    float4 f;
+    __builtin_memcpy(&f, &v, 16);
+    return f;
+}
+
+// Neighbour spinor kept in its storage form (packed halves stay packed) and
+// decoded one colour at a time.  lane: byte offset of the lane's slot field
+// from the resource base; i: site within the parity.
+template <int SP, class T>
+struct Raw;
+template <class T>
+struct Raw<P64, T> {
+    double2 q[12];
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t lane, int vh, int i)
+    {
+        const uint32_t vo = lane + (uint32_t)i * 16u;
+#pragma unroll
+        for (int k = 0; k < 12; k++) q[k] = as_d2(bld16(rs, vo, (uint32_t)k * (uint32_t)vh * 16u));
+    }
+    __device__ __forceinline__ cpx<T> get(int k) const { return cpx<T>{(T)q[k].x, (T)q[k].y}; }
+};
+template <class T>
+struct Raw<P32, T> {
+    float4 q[6];
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t lane, int vh, int i)
+    {
+        const uint32_t vo = lane + (uint32_t)i * 16u;
+#pragma unroll
+        for (int g = 0; g < 6; g++) q[g] = as_f4(bld16(rs, vo, (uint32_t)g * (uint32_t)vh * 16u));
+    }
+    __device__ __forceinline__ cpx<T> get(int k) const
+    {
+        const float4 &v = q[k >> 1];
+        return (k & 1) ? cpx<T>{(T)v.z, (T)v.w} : cpx<T>{(T)v.x, (T)v.y};
+    }
+};
+template <int P, class T>
+struct RawHalf {
+    u32x4 q[3];
+    float sc;
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t lane, int vh, int i)
+    {
+        const uint32_t vo = lane + (uint32_t)i * 16u;
+#pragma unroll
+        for (int g = 0; g < 3; g++) q[g] = bld16(rs, vo, (uint32_t)g * (uint32_t)vh * 16u);
+        sc = __uint_as_float(bld4(rs, lane + (uint32_t)i * 4u, 3u * (uint32_t)vh * 16u));
+    }
+    __device__ __forceinline__ cpx<T> get(int k) const
+    {
+        const u32x4 &v = q[k >> 2];
+        const uint32_t w = v[k & 3];
+        return cpx<T>{(T)(HalfCodec<P>::dec((uint16_t)(w & 0xFFFFu)) * sc),
+                      (T)(HalfCodec<P>::dec((uint16_t)(w >> 16)) * sc)};
+    }
+};
+template <class T>
+struct Raw<P16, T> : RawHalf<P16, T> {};
+template <class T>
+struct Raw<PBF, T> : RawHalf<PBF, T> {};
+
+// Noise neighbour generated from its 4-byte Z4 code: c * eta with c = A^-1
+// per chirality (a prep hop over A^-1 eta_o without any stored spinor).
+template <class T>
+struct RawZ4 {
+    uint32_t code;
+    cpx<T> c[2];
+    __device__ __forceinline__ void load(__amdgpu_buffer_rsrc_t rs, uint32_t lane, int vh, int i)
+    {
+        code = bld4(rs, lane + (uint32_t)i * 4u, 0);
+    }
+    __device__ __forceinline__ cpx<T> get(int k) const
+    {
+        const T h = (T)0.70710678118654752440;
+        const cpx<T> e{((code >> (2 * k)) & 1u) ? -h : h, ((code >> (2 * k + 1)) & 1u) ? -h : h};
+        return cmul(c[k / 6], e);
+    }
+};
+
+// link (par, mu) of site i through the gauge resource
+template <int SP, class T>
+__device__ __forceinline__ void load_link(__amdgpu_buffer_rsrc_t rs, int vh, int par, int mu, int i, Link<T> &L)
+{
+    const uint32_t pm = (uint32_t)(par * 4 + mu);
+    if constexpr (SP == P64) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const double2 q = as_d2(bld16(rs, (uint32_t)i * 16u, (pm * 6u + k) * (uint32_t)vh * 16u));
+            L.u[k / 3][k % 3] = cpx<T>{(T)q.x, (T)q.y};
+        }
+    } else if constexpr (SP == P32) {
+#pragma unroll
+        for (int g = 0; g < 3; g++) {
+            const float4 q = as_f4(bld16(rs, (uint32_t)i * 16u, (pm * 3u + g) * (uint32_t)vh * 16u));
+            L.u[(2 * g) / 3][(2 * g) % 3] = cpx<T>{(T)q.x, (T)q.y};
+            L.u[(2 * g + 1) / 3][(2 * g + 1) % 3] = cpx<T>{(T)q.z, (T)q.w};
+        }
+    } else {
+#pragma unroll
+        for (int g = 0; g < 3; g++) {
+            const u32x2 q = bld8(rs, (uint32_t)i * 8u, (pm * 3u + g) * (uint32_t)vh * 8u);
+            L.u[(2 * g) / 3][(2 * g) % 3] =
+                cpx<T>{(T)HalfCodec<SP>::dec(q.x & 0xFFFFu), (T)HalfCodec<SP>::dec(q.x >> 16)};
+            L.u[(2 * g + 1) / 3][(2 * g + 1) % 3] =
+                cpx<T>{(T)HalfCodec<SP>::dec(q.y & 0xFFFFu), (T)HalfCodec<SP>::dec(q.y >> 16)};
+        }
+    }
+    rebuild_row2(L);
+}
+
+// half spinor of colour c for the projector (1 + S g_mu)
+template <class T, int MU, int S, class R>
+__device__ __forceinline__ void project_c(const R &raw, int c, cpx<T> &h0, cpx<T> &h1)
+{
+    const cpx<T> p0 = raw.get(c), p1 = raw.get(3 + c), p2 = raw.get(6 + c), p3 = raw.get(9 + c);
+    if (MU == 0) {
+        h0 = S > 0 ? p0 - ti(p3) : p0 + ti(p3);
+        h1 = S > 0 ? p1 - ti(p2) : p1 + ti(p2);
+    } else if (MU == 1) {
+        h0 = S > 0 ? p0 - p3 : p0 + p3;
+        h1 = S > 0 ? p1 + p2 : p1 - p2;
+    } else if (MU == 2) {
+        h0 = S > 0 ? p0 - ti(p2) : p0 + ti(p2);
+        h1 = S > 0 ? p1 + ti(p3) : p1 - ti(p3);
+    } else {
+        h0 = S > 0 ? p0 + p2 : p0 - p2;
+        h1 = S > 0 ? p1 + p3 : p1 - p3;
+    }
+}
+
+// w = U h (FWD) or U^dagger h, accumulated colour by colour of h
+template <class T, int MU, int S, bool FWD, class R>
+__device__ __forceinline__ void transport(const Link<T> &L, const R &raw, cpx<T> w[6])
+{
+#pragma unroll
+    for (int k = 0; k < 6; k++) w[k] = cpx<T>{(T)0, (T)0};
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        cpx<T> h0, h1;
+        project_c<T, MU, S>(raw, b, h0, h1);
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (FWD) {
+                w[a] = w[a] + cmul(L.u[a][b], h0);
+                w[3 + a] = w[3 + a] + cmul(L.u[a][b], h1);
+            } else {
+                w[a] = w[a] + cmulc(L.u[b][a], h0);
+                w[3 + a] = w[3 + a] + cmulc(L.u[b][a], h1);
+            }
+        }
+    }
+}
+
+// Resources of one Dslash application (uniform per block).
+struct HopRes {
+    __amdgpu_buffer_rsrc_t in, gauge;
+    uint32_t lane;  // byte offset of this lane's input field from the input resource base
+};
+
+template <class RawT>
+__device__ __forceinline__ void raw_setup(RawT &, double, double) {}
+template <class T>
+__device__ __forceinline__ void raw_setup(RawZ4<T> &z, double den, double a)
+{
+    // A^-1 = (1 - i a g5) / (1 + a^2): chirality + then -
+    z.c[0] = cpx<T>{(T)den, (T)(-a * den)};
+    z.c[1] = cpx<T>{(T)den, (T)(a * den)};
+}
+
+// One neighbour: forward x+mu with (1 - g_mu) U_mu(x), or backward x-mu with
+// (1 + g_mu) U_mu(x-mu)^dagger (projectors swapped for DAG).
+template <class T, int SP, int MU, bool FWD, bool DAG, class RawT>
+__device__ __forceinline__ void hop_dir(const DslashArgs &A, const HopRes &R, const Site &s, cpx<T> acc[12],
+                                        double den, double a)
 {
     const int vh = A.g.vh;
-    {  // forward neighbour, projector (1 - g_mu) [ (1 + g_mu) for DAG ]
-        constexpr int S = DAG ? 1 : -1;
-        const int nf = nbr<MU, 1>(A.g, s);
-        cpx<T> psi[12], h[6], w[6];
-        SpinorIO<SP>::load(in, vh, nf, psi);
-        project<T, MU, S>(psi, h);
-        Link<T> L;
-        LinkIO<SP>::load(A.gauge, vh, A.out_par, MU, s.cb, L);
-        umul(L, h, w);
-        umul(L, h + 3, w + 3);
-        if (MU == 3 && A.g.tbc < 0 && s.t == A.g.L[3] - 1) {
+    constexpr int S = (FWD != DAG) ? -1 : 1;
+    const int n = nbr<MU, FWD ? 1 : -1>(A.g, s);
+    RawT raw;
+    raw_setup(raw, den, a);
+    raw.load(R.in, R.lane, vh, n);
+    Link<T> L;
+    load_link<SP, T>(R.gauge, vh, FWD ? A.out_par : 1 - A.out_par, MU, FWD ? s.cb : n, L);
+    cpx<T> w[6];
+    transport<T, MU, S, FWD>(L, raw, w);
+    if (MU == 3 && A.g.tbc < 0 && s.t == (FWD ? A.g.L[3] - 1 : 0)) {
 #pragma unroll
-            for (int k = 0; k < 6; k++) w[k] = cpx<T>{-w[k].re, -w[k].im};
-        }
-        accum<T, MU, S>(acc, w);
+        for (int k = 0; k < 6; k++) w[k] = cpx<T>{-w[k].re, -w[k].im};
     }
-    {  // backward neighbour, projector (1 + g_mu) [ (1 - g_mu) for DAG ]
-        constexpr int S = DAG ? -1 : 1;
-        const int nb = nbr<MU, -1>(A.g, s);
-        cpx<T> psi[12], h[6], w[6];
-        SpinorIO<SP>::load(in, vh, nb, psi);
-        project<T, MU, S>(psi, h);
-        Link<T> L;
-        LinkIO<SP>::load(A.gauge, vh, 1 - A.out_par, MU, nb, L);
-        udagmul(L, h, w);
-        udagmul(L, h + 3, w + 3);
-        if (MU == 3 && A.g.tbc < 0 && s.t == 0) {
-#pragma unroll
-            for (int k = 0; k < 6; k++) w[k] = cpx<T>{-w[k].re, -w[k].im};
+    accum<T, MU, S>(acc, w);
+}
+
+// The eight neighbours as a runtime loop of uniform branches: each stage is
+// its own basic block, so only one neighbour's operands are live at a time
+// and occupancy (not load hoisting) hides memory latency.
+template <class T, int SP, bool DAG, class RawT>
+__device__ __forceinline__ void hop_all(const DslashArgs &A, const HopRes &R, const Site &s, cpx<T> acc[12],
+                                        double den, double a)
+{
+#pragma unroll 1
+    for (int d = 0; d < 8; d++) {
+        switch (__builtin_amdgcn_readfirstlane(d)) {  // opaque: keeps the stages apart
+        case 0: hop_dir<T, SP, 0, true, DAG, RawT>(A, R, s, acc, den, a); break;
+        case 1: hop_dir<T, SP, 0, false, DAG, RawT>(A, R, s, acc, den, a); break;
+        case 2: hop_dir<T, SP, 1, true, DAG, RawT>(A, R, s, acc, den, a); break;
+        case 3: hop_dir<T, SP, 1, false, DAG, RawT>(A, R, s, acc, den, a); break;
+        case 4: hop_dir<T, SP, 2, true, DAG, RawT>(A, R, s, acc, den, a); break;
+        case 5: hop_dir<T, SP, 2, false, DAG, RawT>(A, R, s, acc, den, a); break;
+        case 6: hop_dir<T, SP, 3, true, DAG, RawT>(A, R, s, acc, den, a); break;
+        default: hop_dir<T, SP, 3, false, DAG, RawT>(A, R, s, acc, den, a); break;
         }
-        accum<T, MU, S>(acc, w);
     }
 }
 
@@ -129,42 +323,103 @@ __device__ __forceinline__ void coefs(int mode, double kappa, double a, cpx<T> P
     }
 }
 
-// SLOT: per-slot solver state (CG chunks) or uniform parameters (operator calls)
-template <int SP, bool DAG, int EPI, bool IN2, bool SLOT>
-__global__ __launch_bounds__(BLOCK) void k_dslash(const DslashArgs A)
+// Registers per lane are capped so that several waves per SIMD keep enough
+// loads in flight: minimum waves per execution unit by storage precision.
+template <int SP>
+constexpr int dslash_waves()
+{
+    return SP == P64 ? TM_DSLASH_WAVES_F64 : SP == P32 ? TM_DSLASH_WAVES_F32 : TM_DSLASH_WAVES_F16;
+}
+
+// Thread mapping: a block holds BLOCK/R sites x R right-hand sides ("slots")
+// of one slot group, lane = site * R + r, so the R lanes of a site sit in the
+// same wave and their link loads hit the same addresses: each link is
+// fetched once per R right-hand sides.  Per-slot reductions are over fixed
+// 64-site tiles (one butterfly per tile), independent of R and of the
+// number of slots, so a slot's sums have the same bits in any batch.
+// SLOT: per-slot solver state (CG chunks) or uniform parameters (operator calls).
+// SRC bit 0: the hop input is A^-1 eta decoded from Z4 codes (parity 1 - out_par);
+// SRC bit 1: the site-local input is eta decoded from codes (parity out_par).
+template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, int R, int SRC = 0>
+__global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const DslashArgs A)
 {
     using T = typename Real<SP>::T;
     constexpr int XR = SP == P64 ? P64 : P32;
-    __shared__ double red[BLOCK / 64];
-    int sblk, slot;
-    if (!map_block(A.nblk_site, A.nslot, A.swz, sblk, slot)) return;
+    constexpr int SPB = BLOCK / R;  // sites per block
+    __shared__ double red[EPI == EPI_PLAIN ? 1 : BLOCK];
+    const int ngroups = (A.nslot + R - 1) / R;
+    int sb, grp;
+    if (!map_block(A.nblk_site, ngroups, A.swz, sb, grp)) return;
+    const int r = threadIdx.x % R, sl = threadIdx.x / R;
+    const int slot = grp * R + r;
+    bool live = slot < A.nslot;
     double kappa = A.kappa_u, a = A.a_u, alpha = 0;
     if constexpr (SLOT) {
-        const SlotState &st = A.st[slot];
-        if (st.status != ST_RUNNING) return;
-        kappa = st.kappa;
-        a = st.a;
-        alpha = st.alpha;
+        // the block leaves only if none of its R slots is running
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < R; q++) {
+            const int sq = grp * R + q;
+            any |= sq < A.nslot && A.st[sq].status == ST_RUNNING;
+        }
+        if (!any) return;
+        if (live) {
+            const SlotState &st = A.st[slot];
+            live = st.status == ST_RUNNING;
+            kappa = st.kappa;
+            a = st.a;
+            alpha = st.alpha;
+        }
     }
     const int vh = A.g.vh;
-    const int cb = sblk * BLOCK + threadIdx.x;
+    // t-walk: the block keeps one spatial chunk of SPB sites and walks tw
+    // consecutive timeslices, so its t+-1 and spatial neighbours come back
+    // from its own recent L2 lines instead of HBM.
+    const int tw = A.twalk;
+    int cb0, tstep;
+    if (tw > 1) {
+        const int zs_per_slice = A.g.v3h / SPB;
+        const int tb = sb / zs_per_slice, zs = sb - tb * zs_per_slice;
+        cb0 = tb * tw * A.g.v3h + zs * SPB + sl;
+        tstep = A.g.v3h;
+    } else {
+        cb0 = sb * SPB + sl;
+        tstep = 0;
+    }
+    for (int it = 0; it < (tw > 1 ? tw : 1); it++) {
+    const int cb = cb0 + it * tstep;
     double part = 0.0;
-    if (cb < vh) {
+    if (live && cb < vh) {
         const Site s = site_of(A.g, cb, A.out_par);
-        const char *in = A.in + (size_t)slot * A.in_slot;
+        HopRes res;
+        res.gauge = mkrsrc(A.gauge, A.gauge_span);
         cpx<T> acc[12];
 #pragma unroll
         for (int k = 0; k < 12; k++) acc[k] = cpx<T>{(T)0, (T)0};
-        hop_mu<T, SP, 0, DAG>(A, s, in, acc);
-        hop_mu<T, SP, 1, DAG>(A, s, in, acc);
-        hop_mu<T, SP, 2, DAG>(A, s, in, acc);
-        hop_mu<T, SP, 3, DAG>(A, s, in, acc);
+        if constexpr (SRC & 1) {
+            res.in = mkrsrc(A.codes + (size_t)slot * A.codes_slot / 4 + (size_t)(1 - A.out_par) * vh,
+                            (uint32_t)vh * 4u);
+            res.lane = 0;
+            hop_all<T, SP, DAG, RawZ4<T>>(A, res, s, acc, 1.0 / (1.0 + a * a), a);
+        } else {
+            res.in = mkrsrc(A.in + (size_t)grp * R * A.in_slot, A.in_span);
+            res.lane = (uint32_t)r * (uint32_t)A.in_slot;
+            hop_all<T, SP, DAG, Raw<SP, T>>(A, res, s, acc, 0.0, 0.0);
+        }
         cpx<T> P[2], Q[2];
         coefs<T>(A.coef, kappa, a, P, Q);
         cpx<T> v[12];
         if (IN2) {
             cpx<T> y[12];
-            SpinorIO<SP>::load(A.in2 + (size_t)slot * A.in2_slot, vh, cb, y);
+            if constexpr (SRC & 2) {
+                const uint32_t c = A.codes[(size_t)slot * A.codes_slot / 4 + (size_t)A.out_par * vh + cb];
+                const T h = (T)0.70710678118654752440;
+#pragma unroll
+                for (int k = 0; k < 12; k++)
+                    y[k] = cpx<T>{((c >> (2 * k)) & 1u) ? -h : h, ((c >> (2 * k + 1)) & 1u) ? -h : h};
+            } else {
+                SpinorIO<SP>::load(A.in2 + (size_t)slot * A.in2_slot, vh, cb, y);
+            }
 #pragma unroll
             for (int k = 0; k < 12; k++) v[k] = cmul(P[k / 6], y[k]) + cmul(Q[k / 6], acc[k]);
         } else {
@@ -178,21 +433,21 @@ __global__ __launch_bounds__(BLOCK) void k_dslash(const DslashArgs A)
                 for (int k = 0; k < 12; k++) part += (double)norm2(v[k]);
             }
         } else if (EPI == EPI_CGUPD) {
-            cpx<T> p[12], x[12], r[12];
+            cpx<T> p[12], x[12], rr[12];
             SpinorIO<SP>::load(A.p + (size_t)slot * A.p_slot, vh, cb, p);
             char *xs = A.x + (size_t)slot * A.xr_slot;
             char *rs = A.r + (size_t)slot * A.xr_slot;
             SpinorIO<XR>::load(xs, vh, cb, x);
-            SpinorIO<XR>::load(rs, vh, cb, r);
+            SpinorIO<XR>::load(rs, vh, cb, rr);
             const T al = (T)alpha;
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 x[k] = x[k] + cscale(al, p[k]);
-                r[k] = r[k] - cscale(al, v[k]);
-                part += (double)norm2(r[k]);
+                rr[k] = rr[k] - cscale(al, v[k]);
+                part += (double)norm2(rr[k]);
             }
             SpinorIO<XR>::store(xs, vh, cb, x);
-            SpinorIO<XR>::store(rs, vh, cb, r);
+            SpinorIO<XR>::store(rs, vh, cb, rr);
         } else {  // EPI_RESID (FP64 only)
             cpx<T> b[12];
             SpinorIO<P64>::load(A.b + (size_t)slot * A.b_slot, vh, cb, b);
@@ -204,21 +459,66 @@ __global__ __launch_bounds__(BLOCK) void k_dslash(const DslashArgs A)
             SpinorIO<SP>::store(A.out + (size_t)slot * A.out_slot, vh, cb, v);
         }
     }
-    if (EPI != EPI_PLAIN) {
-        part = block_sum<BLOCK>(part, red);
-        if (threadIdx.x == 0) A.partial[(size_t)slot * A.nblk_site + sblk] = part;
+    if constexpr (EPI != EPI_PLAIN) {
+        // tile sums: wave w reduces (slot r_w, tile t_w) of this block
+        __syncthreads();  // red[] of the previous t-step fully consumed
+        red[r * SPB + sl] = part;
+        __syncthreads();
+        constexpr int TPS = SPB / 64;  // tiles per slot in this block
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int rw = w / TPS, tw_ = w % TPS;
+        const double v = wave_sum(red[rw * SPB + tw_ * 64 + lane]);
+        const int sw = grp * R + rw;
+        const int tile = (cb - sl) / 64 + tw_;
+        if (lane == 0 && sw < A.nslot && tile < A.ntile) A.partial[(size_t)sw * A.ntile + tile] = v;
+    }
     }
 }
 
-template <int SP, bool DAG, int EPI, bool IN2>
-static void launch_t(const DslashArgs &A, hipStream_t s)
+template <int SP, bool DAG, int EPI, bool IN2, int R>
+static void launch_r(const DslashArgs &A, hipStream_t s)
 {
-    const int total = A.nblk_site * A.nslot;
+    const int ngroups = (A.nslot + R - 1) / R;
+    const int total = A.nblk_site * ngroups;
     const int grid = A.swz ? 8 * ((total + 7) / 8) : total;
     if (A.st)
-        hipLaunchKernelGGL((k_dslash<SP, DAG, EPI, IN2, true>), dim3(grid), dim3(BLOCK), 0, s, A);
+        hipLaunchKernelGGL((k_dslash<SP, DAG, EPI, IN2, true, R>), dim3(grid), dim3(BLOCK), 0, s, A);
     else
-        hipLaunchKernelGGL((k_dslash<SP, DAG, EPI, IN2, false>), dim3(grid), dim3(BLOCK), 0, s, A);
+        hipLaunchKernelGGL((k_dslash<SP, DAG, EPI, IN2, false, R>), dim3(grid), dim3(BLOCK), 0, s, A);
+}
+
+// timeslices walked per block (TM_TWALK overrides; 1 = no walk)
+inline int dslash_twalk()
+{
+    static int tw = [] {
+        const char *e = getenv("TM_TWALK");
+        return e ? std::max(1, atoi(e)) : 4;
+    }();
+    return tw;
+}
+
+// lanes per site: one per slot up to 4
+inline int lanes_per_site(int nslot) { return nslot >= 3 ? 4 : nslot; }
+
+template <int SP, bool DAG, int EPI, bool IN2>
+static void launch_t(DslashArgs A, hipStream_t s)
+{
+    int R = lanes_per_site(A.nslot);
+    // 32-bit buffer offsets: the R input fields of a group must span < 4 GiB
+    const uint64_t field = (uint64_t)A.g.vh * (SP == P64 ? 192 : SP == P32 ? 96 : 52);
+    if (R > 1 && ((uint64_t)(R - 1) * A.in_slot + field >= (1ull << 32) || A.in_slot % 16)) R = 1;
+    A.in_span = (uint32_t)std::min<uint64_t>((uint64_t)(R - 1) * A.in_slot + field, 0xFFFFFFFFull);
+    A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : SP == P32 ? 48 : 24),
+                                                0xFFFFFFFFull);
+    const int spb = BLOCK / R;
+    int tw = dslash_twalk();
+    if (tw > 1 && (A.g.v3h % spb != 0 || A.g.L[3] % tw != 0)) tw = 1;
+    A.twalk = tw;
+    A.nblk_site = tw > 1 ? A.g.vh / spb / tw : (A.g.vh + spb - 1) / spb;
+    A.ntile = ntile_of(A.g);
+    if (R == 1) launch_r<SP, DAG, EPI, IN2, 1>(A, s);
+    else if (R == 2) launch_r<SP, DAG, EPI, IN2, 2>(A, s);
+    else launch_r<SP, DAG, EPI, IN2, 4>(A, s);
 }
 
 template <int SP>
@@ -241,9 +541,32 @@ static void launch_sp(bool dag, int epi, bool in2, const DslashArgs &A, hipStrea
 #undef TMK_CASE
 }
 
+// Z4-code sources (prep and reconstruction of noise solves), FP32 and FP64.
+template <int SP, int SRC>
+static void launch_src(DslashArgs A, hipStream_t s)
+{
+    A.twalk = 1;
+    A.nblk_site = (A.g.vh + BLOCK - 1) / BLOCK;
+    A.ntile = ntile_of(A.g);
+    A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : 48), 0xFFFFFFFFull);
+    A.in_span = (uint32_t)std::min<uint64_t>((uint64_t)A.g.vh * (SP == P64 ? 192 : 96), 0xFFFFFFFFull);
+    const int total = A.nblk_site * A.nslot;
+    const int grid = A.swz ? 8 * ((total + 7) / 8) : total;
+    hipLaunchKernelGGL((k_dslash<SP, false, EPI_PLAIN, true, false, 1, SRC>), dim3(grid), dim3(BLOCK), 0, s, A);
+}
+
+int launch_dslash_codes(int sp, int src, const DslashArgs &A, hipStream_t s)
+{
+    if (sp != P64 && sp != P32) return -1;
+    if (src == 3) sp == P64 ? launch_src<P64, 3>(A, s) : launch_src<P32, 3>(A, s);
+    else if (src == 2) sp == P64 ? launch_src<P64, 2>(A, s) : launch_src<P32, 2>(A, s);
+    else return -1;
+    return 0;
+}
+
 int launch_dslash(int sp, bool dag, int epi, bool in2, const DslashArgs &A, hipStream_t s)
 {
-    if (A.nslot < 1 || A.nblk_site < 1) return 0;
+    if (A.nslot < 1) return 0;
     if (epi == EPI_RESID && sp != P64) return -1;
     if ((epi == EPI_NORM || epi == EPI_CGUPD || epi == EPI_RESID) && !in2) return -1;
     switch (sp) {

@@ -81,7 +81,7 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 //   kind 5+nu:   B_ab  = sum conj([U_nu(x) eta(x+nu)]_a) . s_b(x)
 // ---------------------------------------------------------------------------
 constexpr int CT = 128;        // threads per contraction block
-constexpr int SPT = 4;         // sites per thread
+constexpr int SPT = 8;         // sites per thread (amortises the block reductions)
 constexpr int CPB = CT * SPT;  // sites per block
 
 int contract_nchunk(const Geom &g) { return (2 * g.v3h + CPB - 1) / CPB; }
@@ -114,81 +114,22 @@ __device__ __forceinline__ bool contract_site(const Geom &g, int t, int q, int &
     return true;
 }
 
-template <int NU>
-__device__ __forceinline__ void contract_dir(const Geom &g, const void *G, const char *s_fld[2],
-                                             const uint32_t *codes, int t, int chunk, double (&acc)[64])
+// One kind of spin matrix for the thread's sites, 32 accumulators:
+//   KIND 0: local; KIND 1+nu: F^nu; KIND 5+nu: B^nu.
+template <int KIND, int SPS>
+__device__ __forceinline__ void contract_kind(const Geom &g, const void *G, const char *s_fld[2],
+                                              const uint32_t *codes, int t, int chunk, double (&acc)[32])
 {
+#pragma unroll
+    for (int k = 0; k < 32; k++) acc[k] = 0.0;
+#pragma unroll 1
     for (int k = 0; k < SPT; k++) {
         int par, cb;
         if (!contract_site(g, t, chunk * CPB + k * CT + threadIdx.x, par, cb)) continue;
-        const Site s = site_of(g, cb, par);
-        const int nf = nbr<NU, 1>(g, s);
         const uint32_t ce = codes[(size_t)par * g.vh + cb];
-        const uint32_t cf = codes[(size_t)(1 - par) * g.vh + nf];
-        Link<double> L;
-        LinkIO<P64>::load(G, g.vh, par, NU, cb, L);
-        const double sg = (NU == 3 && g.tbc < 0 && s.t == g.L[3] - 1) ? -1.0 : 1.0;
-        const double2 *sn = (const double2 *)s_fld[1 - par];
-        const double2 *sx = (const double2 *)s_fld[par];
-        // F: conj(eta_a(x)) . (U s(x+nu))_b
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            cpx<double> h[3], w[3];
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const double2 q = sn[(size_t)(3 * b + c) * g.vh + nf];
-                h[c] = cpx<double>{sg * q.x, sg * q.y};
-            }
-            umul(L, h, w);
-#pragma unroll
-            for (int a = 0; a < 4; a++) {
-                cpx<double> f = cmulc(z4_unscaled<double>(ce, 3 * a), w[0]) +
-                                cmulc(z4_unscaled<double>(ce, 3 * a + 1), w[1]) +
-                                cmulc(z4_unscaled<double>(ce, 3 * a + 2), w[2]);
-                acc[2 * (4 * a + b)] += f.re;
-                acc[2 * (4 * a + b) + 1] += f.im;
-            }
-        }
-        // B: conj((U eta(x+nu))_a) . s_b(x)
-        cpx<double> sv[12];
-        SpinorIO<P64>::load(sx, g.vh, cb, sv);
-#pragma unroll
-        for (int a = 0; a < 4; a++) {
-            cpx<double> e[3], v[3];
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const cpx<double> z = z4_unscaled<double>(cf, 3 * a + c);
-                e[c] = cpx<double>{sg * z.re, sg * z.im};
-            }
-            umul(L, e, v);
-#pragma unroll
-            for (int b = 0; b < 4; b++) {
-                cpx<double> f = cmulc(v[0], sv[3 * b]) + cmulc(v[1], sv[3 * b + 1]) + cmulc(v[2], sv[3 * b + 2]);
-                acc[32 + 2 * (4 * a + b)] += f.re;
-                acc[32 + 2 * (4 * a + b) + 1] += f.im;
-            }
-        }
-    }
-}
-
-// partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
-__global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd,
-                                                 const uint32_t *codes, double *cpart, int nchunk)
-{
-    __shared__ double lds[(CT / 64) * 64];
-    const int t = blockIdx.x / nchunk, chunk = blockIdx.x - t * nchunk;
-    const char *s_fld[2] = {s_even, s_odd};
-    double *dst = cpart + (size_t)blockIdx.x * 288;
-    {  // local
-        double acc[32];
-#pragma unroll
-        for (int k = 0; k < 32; k++) acc[k] = 0.0;
-        for (int k = 0; k < SPT; k++) {
-            int par, cb;
-            if (!contract_site(g, t, chunk * CPB + k * CT + threadIdx.x, par, cb)) continue;
-            const uint32_t ce = codes[(size_t)par * g.vh + cb];
+        if constexpr (KIND == 0) {
             cpx<double> sv[12];
-            SpinorIO<P64>::load(s_fld[par], g.vh, cb, sv);
+            SpinorIO<SPS>::load(s_fld[par], g.vh, cb, sv);
 #pragma unroll
             for (int a = 0; a < 4; a++)
 #pragma unroll
@@ -199,25 +140,81 @@ __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const ch
                     acc[2 * (4 * a + b)] += f.re;
                     acc[2 * (4 * a + b) + 1] += f.im;
                 }
+        } else {
+            constexpr int NU = (KIND - 1) % 4;
+            const Site s = site_of(g, cb, par);
+            const int nf = nbr<NU, 1>(g, s);
+            Link<double> L;
+            LinkIO<P64>::load(G, g.vh, par, NU, cb, L);
+            const double sg = (NU == 3 && g.tbc < 0 && s.t == g.L[3] - 1) ? -1.0 : 1.0;
+            if constexpr (KIND <= 4) {
+                // F: conj(eta_a(x)) . (U s(x+nu))_b
+                cpx<double> snb[12];
+                SpinorIO<SPS>::load(s_fld[1 - par], g.vh, nf, snb);
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    cpx<double> h[3], w[3];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) h[c] = cpx<double>{sg * snb[3 * b + c].re, sg * snb[3 * b + c].im};
+                    umul(L, h, w);
+#pragma unroll
+                    for (int a = 0; a < 4; a++) {
+                        cpx<double> f = cmulc(z4_unscaled<double>(ce, 3 * a), w[0]) +
+                                        cmulc(z4_unscaled<double>(ce, 3 * a + 1), w[1]) +
+                                        cmulc(z4_unscaled<double>(ce, 3 * a + 2), w[2]);
+                        acc[2 * (4 * a + b)] += f.re;
+                        acc[2 * (4 * a + b) + 1] += f.im;
+                    }
+                }
+            } else {
+                // B: conj((U eta(x+nu))_a) . s_b(x)
+                const uint32_t cf = codes[(size_t)(1 - par) * g.vh + nf];
+                cpx<double> sv[12];
+                SpinorIO<SPS>::load(s_fld[par], g.vh, cb, sv);
+#pragma unroll
+                for (int a = 0; a < 4; a++) {
+                    cpx<double> e[3], v[3];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) {
+                        const cpx<double> z = z4_unscaled<double>(cf, 3 * a + c);
+                        e[c] = cpx<double>{sg * z.re, sg * z.im};
+                    }
+                    umul(L, e, v);
+#pragma unroll
+                    for (int b = 0; b < 4; b++) {
+                        cpx<double> f = cmulc(v[0], sv[3 * b]) + cmulc(v[1], sv[3 * b + 1]) + cmulc(v[2], sv[3 * b + 2]);
+                        acc[2 * (4 * a + b)] += f.re;
+                        acc[2 * (4 * a + b) + 1] += f.im;
+                    }
+                }
+            }
         }
-        block_write<32>(acc, lds, dst);
     }
-#define TMK_DIR(NU)                                                        \
-    {                                                                      \
-        double acc[64];                                                    \
-        _Pragma("unroll") for (int k = 0; k < 64; k++) acc[k] = 0.0;       \
-        contract_dir<NU>(g, G, s_fld, codes, t, chunk, acc);               \
-        double tmp[32];                                                    \
-        _Pragma("unroll") for (int k = 0; k < 32; k++) tmp[k] = acc[k];    \
-        block_write<32>(tmp, lds, dst + (1 + NU) * 32);                    \
-        _Pragma("unroll") for (int k = 0; k < 32; k++) tmp[k] = acc[32 + k]; \
-        block_write<32>(tmp, lds, dst + (5 + NU) * 32);                    \
-    }
-    TMK_DIR(0)
-    TMK_DIR(1)
-    TMK_DIR(2)
-    TMK_DIR(3)
-#undef TMK_DIR
+}
+
+// partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
+template <int SPS>
+__global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd,
+                                                 const uint32_t *codes, double *cpart, int nchunk)
+{
+    __shared__ double lds[(CT / 64) * 32];
+    const int t = blockIdx.x / nchunk, chunk = blockIdx.x - t * nchunk;
+    const char *s_fld[2] = {s_even, s_odd};
+    double *dst = cpart + (size_t)blockIdx.x * 288;
+    double acc[32];
+#define TMK_KIND(K)                                                  \
+    contract_kind<K, SPS>(g, G, s_fld, codes, t, chunk, acc);        \
+    block_write<32>(acc, lds, dst + (K) * 32);
+    TMK_KIND(0)
+    TMK_KIND(1)
+    TMK_KIND(2)
+    TMK_KIND(3)
+    TMK_KIND(4)
+    TMK_KIND(5)
+    TMK_KIND(6)
+    TMK_KIND(7)
+    TMK_KIND(8)
+#undef TMK_KIND
 }
 
 // raw[kind][t][ab][2] = 2^-1/2 * sum_chunk cpart[t][chunk][kind][ab][2]
@@ -232,13 +229,17 @@ __global__ void k_contract_final(const double *cpart, int nchunk, int lt, double
     raw[((size_t)kind * lt + t) * 32 + ab] = s * TM_RSQRT2;
 }
 
-void launch_contract(const Geom &g, const void *gauge64, const char *s_even, const char *s_odd,
+void launch_contract(int sps, const Geom &g, const void *gauge64, const char *s_even, const char *s_odd,
                      const uint32_t *codes, double *cpart, double *raw_out, hipStream_t s)
 {
     const int nchunk = contract_nchunk(g);
     const int lt = g.L[3];
-    hipLaunchKernelGGL(k_contract, dim3(lt * nchunk), dim3(CT), 0, s, g, gauge64, s_even, s_odd, codes, cpart,
-                       nchunk);
+    if (sps == P32)
+        hipLaunchKernelGGL((k_contract<P32>), dim3(lt * nchunk), dim3(CT), 0, s, g, gauge64, s_even, s_odd, codes,
+                           cpart, nchunk);
+    else
+        hipLaunchKernelGGL((k_contract<P64>), dim3(lt * nchunk), dim3(CT), 0, s, g, gauge64, s_even, s_odd, codes,
+                           cpart, nchunk);
     const int n = lt * 288;
     hipLaunchKernelGGL(k_contract_final, dim3((n + 255) / 256), dim3(256), 0, s, cpart, nchunk, lt, raw_out);
 }

@@ -100,7 +100,8 @@ struct Batch {
     int S = 1;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    size_t hsp = 0, hxr = 0, h64 = 0;
+    size_t hsp = 0, hxr = 0;  // slot pitches of the CG fields (padded)
+    size_t h64 = 0;           // FP64 half field (unpadded: scratch halves are adjacent)
     char *p = nullptr, *u = nullptr, *t = nullptr, *x = nullptr, *r = nullptr;
     char *x64 = nullptr, *b64 = nullptr;
     uint32_t *codes = nullptr;

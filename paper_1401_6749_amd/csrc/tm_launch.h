@@ -11,6 +11,10 @@ namespace tmk {
 // same precision), x/r in FP64 for sp = P64 else FP32.  Returns -1 on an
 // unsupported combination.
 int launch_dslash(int sp, bool dag, int epi, bool in2, const DslashArgs &A, hipStream_t s);
+// plain-epilogue Dslash with Z4-code inputs, uniform (kappa, a):
+//   src 3: hop input A^-1 eta (parity 1 - out_par) and site input eta (prep: bhat = eta + k D A^-1 eta)
+//   src 2: hop input a field, site input eta (reconstruction: A^-1 (eta + k D s))
+int launch_dslash_codes(int sp, int src, const DslashArgs &A, hipStream_t s);
 
 // ---- CG scalars (one block per slot, fixed summation order) ----
 void launch_cg_alpha(SlotState *st, const double *partial, int nslot, int nblk, hipStream_t s);
@@ -32,7 +36,7 @@ void launch_convert(int pin, int pout, const Geom &g, const char *in, size_t in_
 void launch_zero(int p, const Geom &g, char *f, size_t slot, int nslot, hipStream_t s);
 // x64 += x32; x32 = 0
 void launch_accum_x(const Geom &g, char *x64, const char *x32_in, char *x32_zero, hipStream_t s);
-// per-block |f|^2 partials of one FP64 half field
+// per-tile (64 sites) |f|^2 partials of one FP64 half field
 void launch_norm_partial(const Geom &g, const char *f, double *partial, hipStream_t s);
 // out = c * in with c per chirality: A^-1 (mode 1) or identity (mode 0), FP64
 void launch_site_diag(const Geom &g, int mode, double a, const char *in, char *out, hipStream_t s);
@@ -47,8 +51,9 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 
 // ---- contractions ----
 int contract_nchunk(const Geom &g);
-// spin matrices of one source into raw_out [9][T][16][2] (FP64)
-void launch_contract(const Geom &g, const void *gauge64, const char *s_even, const char *s_odd,
+// spin matrices of one source into raw_out [9][T][16][2]: s in FP64 or FP32
+// (sps), links FP64, accumulation FP64
+void launch_contract(int sps, const Geom &g, const void *gauge64, const char *s_even, const char *s_odd,
                      const uint32_t *codes, double *cpart, double *raw_out, hipStream_t s);
 // raw [n][9][T][16][2] -> ops [n][90][T][2]; gtab: [16][4] (col | phase << 2)
 void launch_project(int n, int lt, const double *raw, double *ops, const int *gtab_host, hipStream_t s);
@@ -79,5 +84,7 @@ inline size_t link_array_bytes(int p, const Geom &g)
     return (size_t)2 * 4 * g.vh * (p == P64 ? 96 : p == P32 ? 48 : 24);
 }
 __host__ __device__ inline int nblk_of(const Geom &g) { return (g.vh + BLOCK - 1) / BLOCK; }
+// per-slot partial sums: one per 64-site tile
+__host__ __device__ inline int ntile_of(const Geom &g) { return (g.vh + TILE - 1) / TILE; }
 
 }  // namespace tmk

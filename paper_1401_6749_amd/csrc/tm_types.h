@@ -108,6 +108,7 @@ enum : int {
 
 constexpr int MAX_SLOTS = 16;
 constexpr int BLOCK = 256;  // threads per block of the site kernels
+constexpr int TILE = 64;    // sites per reduction tile (partials are per slot and tile)
 
 struct DslashArgs {
     Geom g;
@@ -120,8 +121,11 @@ struct DslashArgs {
     int coef;
     double kappa_u, a_u;  // used when st == nullptr
     SlotState *st;
-    int nslot, nblk_site, swz;
-    double *partial;  // [nslot][nblk_site]
+    int nslot, nblk_site, swz;  // nblk_site: blocks over the sites (set by the launcher)
+    int ntile;                  // 64-site reduction tiles per slot
+    uint32_t in_span, gauge_span;  // bytes reachable through the buffer resources (set by the launcher)
+    int twalk;                     // timeslices walked per block (set by the launcher)
+    double *partial;            // [nslot][ntile]
     // EPI_CGUPD
     char *x, *r;
     const char *p;
@@ -129,6 +133,9 @@ struct DslashArgs {
     // EPI_RESID
     const char *b;
     size_t b_slot;
+    // Z4-code inputs: codes[par * V/2 + cb] per slot, slot stride in bytes
+    const uint32_t *codes;
+    size_t codes_slot;
 };
 
 }  // namespace tmk

@@ -224,3 +224,25 @@ def test_loops_plain_estimator_c1(oracle):
     ref = oracle.loops_tsm(dims, -1, U, 0.12, 0.01, 101, 0, 16, lp_tol=1e-10)
     assert GU.relerr(r["est"], ref["est"]) < 1e-10
     assert np.allclose(r["var_re"], ref["var_re"], rtol=1e-7)
+
+
+@pytest.mark.parametrize("half", ["f16", "bf16"])
+def test_lp_noise_path_matched_iterations(oracle, half):
+    """LP noise solves (FP32 preparation from the Z4 codes, half-precision CG,
+    FP32 reconstruction, contraction of FP32 s with FP64 accumulation) at a
+    fixed iteration count against the oracle's FP64 solve of the same source
+    with the same count: the difference is the storage rounding only."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (8, 6, 4, 10)
+    U = inputs.gauge_field(dims, seed=6)
+    g = GU.load(dims, U)
+    kappa, a = 0.1636, 0.0033
+    P = tm.tsm_params(kappa, a, 77, 0, 3, lp=tm.solver_params("lp", fixed_iters=5, half=half), batch=2)
+    r = tm.tm_loops_tsm(ctx, g, P, dims[3], want_raw=True)
+    ref = oracle.loops_tsm(dims, -1, U, kappa, a, 77, 0, 3, lp_fixed_iters=5, return_raw=True)
+    tol = 5e-3 if half == "f16" else 3e-2
+    for j in range(3):
+        assert GU.relerr(r["raw_lp"][j], ref["lp_raw"][j]) < tol, (j, GU.relerr(r["raw_lp"][j], ref["lp_raw"][j]))
+    assert r["stats"]["lp_iters"] == 15
