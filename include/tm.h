@@ -298,6 +298,11 @@ int tm_serve_create(tm_context *ctx, int slots, size_t workspace_budget, tm_serv
 /* Queue a request (copied).  Errors: TM_ERR_ARG, TM_ERR_NOMEM (the
  * request's footprint can never fit the workspace budget). */
 int tm_serve_submit(tm_server *srv, const tm_request *req);
+/* Workspace bytes *bytes that req needs from the budget when none of its
+ * batches is resident yet (its output buffers plus fresh batches for its
+ * HP and LP precisions).  Capacity planning only; queues nothing.
+ * Errors: TM_ERR_ARG. */
+int tm_serve_footprint(const tm_server *srv, const tm_request *req, size_t *bytes);
 /* Pop up to max finished results into out[] (returns the count, or < 0). */
 int tm_serve_poll(tm_server *srv, tm_result *out, int max);
 /* Block until every submitted request is finished. */

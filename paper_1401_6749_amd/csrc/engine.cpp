@@ -37,7 +37,7 @@ int kind_prec(Kind k)
     return P64;
 }
 
-static int kind_xr(Kind k) { return k == K_F64 ? P64 : P32; }
+static int kind_xr(Kind k) { return kind_prec(k); }  // x, r stored like the Dslash operands
 
 // Pitch between the slots of a multi-slot field: the field plus 17 x 256
 // bytes, so the same site of consecutive slots (at power-of-two-sized
@@ -290,12 +290,13 @@ int batch_fill(Batch *b, int slot, Job *j)
         dsl_codes(b, pp, 3, CM_PREP, 0, slot, nullptr, Be, j->kappa, j->a);
         dsl(b, pp, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, nullptr, To, j->kappa, j->a);
         if (pp == P32) {
-            // LP: the right-hand side lands directly in r (FP32)
-            char *r = b->r + slot * b->hxr;
-            dsl(b, P32, true, EPI_NORM, CM_MHAT_DAG, 0, To, Be, r, j->kappa, j->a, part);
+            // LP: the FP32 right-hand side is rounded once into r and p (half precision)
+            char *rhs = b->FA;
+            dsl(b, P32, true, EPI_NORM, CM_MHAT_DAG, 0, To, Be, rhs, j->kappa, j->a, part);
             launch_slot_start(b->st + slot, part, b->nblk, j->kappa, j->a, tol2, maxit, delta * delta, 0, s);
-            launch_convert(P32, b->sp, g, r, 0, b->p + slot * b->hsp, 0, 1, s);
-            launch_zero(P32, g, b->x + slot * b->hxr, 0, 1, s);
+            launch_convert(P32, b->xr, g, rhs, 0, b->r + slot * b->hxr, 0, 1, s);
+            launch_convert(P32, b->sp, g, rhs, 0, b->p + slot * b->hsp, 0, 1, s);
+            launch_zero(b->xr, g, b->x + slot * b->hxr, 0, 1, s);
             return TM_OK;
         }
         char *Ce = b->FA;
@@ -456,13 +457,13 @@ static int harvest(Batch *b, int slot, const SlotState &S)
     Job *j = b->slot_job[slot];
     hipStream_t s = b->stream;
     if (prep_prec(b, j) == P32) {
-        // LP noise solve: s_e = x (FP32), s_o = A^-1 (eta_o + kappa D_oe s_e) from the codes,
-        // contraction on FP32 s with FP64 accumulation
-        const char *se32 = b->x + slot * b->hxr;
-        char *so32 = b->FC;
+        // LP noise solve: s_e = x widened to FP32, s_o = A^-1 (eta_o + kappa D_oe s_e) from the
+        // codes, contraction on FP32 s and FP32 links with FP64 accumulation
+        char *se32 = b->FB, *so32 = b->FC;
+        launch_convert(b->xr, P32, g, b->x + slot * b->hxr, 0, se32, 0, 1, s);
         dsl_codes(b, P32, 2, CM_RECON, 1, slot, se32, so32, j->kappa, j->a);
         if (j->raw_out)
-            launch_contract(P32, g, b->G->links[P64], se32, so32, b->codes + (size_t)slot * 2 * g.vh, b->cpart,
+            launch_contract(P32, g, b->G->links[P32], se32, so32, b->codes + (size_t)slot * 2 * g.vh, b->cpart,
                             j->raw_out, s);
     } else {
         harvest64(b, slot, S, j);
@@ -498,7 +499,7 @@ static void harvest64(Batch *b, int slot, const SlotState &S, Job *j)
         if (S.status != ST_CONVERGED) launch_accum_x(g, x64, b->x + slot * b->hxr, nullptr, s);
         launch_convert(P64, P64, g, x64, 0, se, 0, 1, s);
     } else {
-        launch_convert(P32, P64, g, b->x + slot * b->hxr, 0, se, 0, 1, s);
+        launch_convert(b->xr, P64, g, b->x + slot * b->hxr, 0, se, 0, 1, s);
     }
     char *Eo = b->FA + b->h64;
     if (j->noise) {

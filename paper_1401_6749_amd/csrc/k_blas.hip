@@ -185,8 +185,8 @@ void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, cons
     }
     TMK_P(P64, P64)
     TMK_P(P32, P32)
-    TMK_P(P16, P32)
-    TMK_P(PBF, P32)
+    TMK_P(P16, P16)
+    TMK_P(PBF, PBF)
 #undef TMK_P
 }
 

@@ -344,7 +344,7 @@ template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, int R, int SRC = 0>
 __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const DslashArgs A)
 {
     using T = typename Real<SP>::T;
-    constexpr int XR = SP == P64 ? P64 : P32;
+    constexpr int XR = SP;  // x and r share the storage precision of the Dslash operands
     constexpr int SPB = BLOCK / R;  // sites per block
     __shared__ double red[EPI == EPI_PLAIN ? 1 : BLOCK];
     const int ngroups = (A.nslot + R - 1) / R;

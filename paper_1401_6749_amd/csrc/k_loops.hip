@@ -114,12 +114,15 @@ __device__ __forceinline__ bool contract_site(const Geom &g, int t, int q, int &
     return true;
 }
 
-// One kind of spin matrix for the thread's sites, 32 accumulators:
+// One kind of spin matrix for the thread's sites, 32 FP64 accumulators:
 //   KIND 0: local; KIND 1+nu: F^nu; KIND 5+nu: B^nu.
+// Products in the precision of s (FP64 for HP and FP64 solves, FP32 for LP
+// solves, with links of the same precision); sums always in FP64.
 template <int KIND, int SPS>
 __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, const char *s_fld[2],
                                               const uint32_t *codes, int t, int chunk, double (&acc)[32])
 {
+    using T = typename Real<SPS>::T;
 #pragma unroll
     for (int k = 0; k < 32; k++) acc[k] = 0.0;
 #pragma unroll 1
@@ -128,63 +131,63 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
         if (!contract_site(g, t, chunk * CPB + k * CT + threadIdx.x, par, cb)) continue;
         const uint32_t ce = codes[(size_t)par * g.vh + cb];
         if constexpr (KIND == 0) {
-            cpx<double> sv[12];
+            cpx<T> sv[12];
             SpinorIO<SPS>::load(s_fld[par], g.vh, cb, sv);
 #pragma unroll
             for (int a = 0; a < 4; a++)
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
-                    cpx<double> f = cmulc(z4_unscaled<double>(ce, 3 * a), sv[3 * b]) +
-                                    cmulc(z4_unscaled<double>(ce, 3 * a + 1), sv[3 * b + 1]) +
-                                    cmulc(z4_unscaled<double>(ce, 3 * a + 2), sv[3 * b + 2]);
-                    acc[2 * (4 * a + b)] += f.re;
-                    acc[2 * (4 * a + b) + 1] += f.im;
+                    cpx<T> f = cmulc(z4_unscaled<T>(ce, 3 * a), sv[3 * b]) +
+                                    cmulc(z4_unscaled<T>(ce, 3 * a + 1), sv[3 * b + 1]) +
+                                    cmulc(z4_unscaled<T>(ce, 3 * a + 2), sv[3 * b + 2]);
+                    acc[2 * (4 * a + b)] += (double)f.re;
+                    acc[2 * (4 * a + b) + 1] += (double)f.im;
                 }
         } else {
             constexpr int NU = (KIND - 1) % 4;
             const Site s = site_of(g, cb, par);
             const int nf = nbr<NU, 1>(g, s);
-            Link<double> L;
-            LinkIO<P64>::load(G, g.vh, par, NU, cb, L);
-            const double sg = (NU == 3 && g.tbc < 0 && s.t == g.L[3] - 1) ? -1.0 : 1.0;
+            Link<T> L;
+            LinkIO<SPS>::load(G, g.vh, par, NU, cb, L);
+            const T sg = (NU == 3 && g.tbc < 0 && s.t == g.L[3] - 1) ? (T)-1 : (T)1;
             if constexpr (KIND <= 4) {
                 // F: conj(eta_a(x)) . (U s(x+nu))_b
-                cpx<double> snb[12];
+                cpx<T> snb[12];
                 SpinorIO<SPS>::load(s_fld[1 - par], g.vh, nf, snb);
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
-                    cpx<double> h[3], w[3];
+                    cpx<T> h[3], w[3];
 #pragma unroll
-                    for (int c = 0; c < 3; c++) h[c] = cpx<double>{sg * snb[3 * b + c].re, sg * snb[3 * b + c].im};
+                    for (int c = 0; c < 3; c++) h[c] = cpx<T>{sg * snb[3 * b + c].re, sg * snb[3 * b + c].im};
                     umul(L, h, w);
 #pragma unroll
                     for (int a = 0; a < 4; a++) {
-                        cpx<double> f = cmulc(z4_unscaled<double>(ce, 3 * a), w[0]) +
-                                        cmulc(z4_unscaled<double>(ce, 3 * a + 1), w[1]) +
-                                        cmulc(z4_unscaled<double>(ce, 3 * a + 2), w[2]);
-                        acc[2 * (4 * a + b)] += f.re;
-                        acc[2 * (4 * a + b) + 1] += f.im;
+                        cpx<T> f = cmulc(z4_unscaled<T>(ce, 3 * a), w[0]) +
+                                        cmulc(z4_unscaled<T>(ce, 3 * a + 1), w[1]) +
+                                        cmulc(z4_unscaled<T>(ce, 3 * a + 2), w[2]);
+                        acc[2 * (4 * a + b)] += (double)f.re;
+                        acc[2 * (4 * a + b) + 1] += (double)f.im;
                     }
                 }
             } else {
                 // B: conj((U eta(x+nu))_a) . s_b(x)
                 const uint32_t cf = codes[(size_t)(1 - par) * g.vh + nf];
-                cpx<double> sv[12];
+                cpx<T> sv[12];
                 SpinorIO<SPS>::load(s_fld[par], g.vh, cb, sv);
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
-                    cpx<double> e[3], v[3];
+                    cpx<T> e[3], v[3];
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        const cpx<double> z = z4_unscaled<double>(cf, 3 * a + c);
-                        e[c] = cpx<double>{sg * z.re, sg * z.im};
+                        const cpx<T> z = z4_unscaled<T>(cf, 3 * a + c);
+                        e[c] = cpx<T>{sg * z.re, sg * z.im};
                     }
                     umul(L, e, v);
 #pragma unroll
                     for (int b = 0; b < 4; b++) {
-                        cpx<double> f = cmulc(v[0], sv[3 * b]) + cmulc(v[1], sv[3 * b + 1]) + cmulc(v[2], sv[3 * b + 2]);
-                        acc[2 * (4 * a + b)] += f.re;
-                        acc[2 * (4 * a + b) + 1] += f.im;
+                        cpx<T> f = cmulc(v[0], sv[3 * b]) + cmulc(v[1], sv[3 * b + 1]) + cmulc(v[2], sv[3 * b + 2]);
+                        acc[2 * (4 * a + b)] += (double)f.re;
+                        acc[2 * (4 * a + b) + 1] += (double)f.im;
                     }
                 }
             }
@@ -229,16 +232,16 @@ __global__ void k_contract_final(const double *cpart, int nchunk, int lt, double
     raw[((size_t)kind * lt + t) * 32 + ab] = s * TM_RSQRT2;
 }
 
-void launch_contract(int sps, const Geom &g, const void *gauge64, const char *s_even, const char *s_odd,
+void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
                      const uint32_t *codes, double *cpart, double *raw_out, hipStream_t s)
 {
     const int nchunk = contract_nchunk(g);
     const int lt = g.L[3];
     if (sps == P32)
-        hipLaunchKernelGGL((k_contract<P32>), dim3(lt * nchunk), dim3(CT), 0, s, g, gauge64, s_even, s_odd, codes,
+        hipLaunchKernelGGL((k_contract<P32>), dim3(lt * nchunk), dim3(CT), 0, s, g, gauge, s_even, s_odd, codes,
                            cpart, nchunk);
     else
-        hipLaunchKernelGGL((k_contract<P64>), dim3(lt * nchunk), dim3(CT), 0, s, g, gauge64, s_even, s_odd, codes,
+        hipLaunchKernelGGL((k_contract<P64>), dim3(lt * nchunk), dim3(CT), 0, s, g, gauge, s_even, s_odd, codes,
                            cpart, nchunk);
     const int n = lt * 288;
     hipLaunchKernelGGL(k_contract_final, dim3((n + 255) / 256), dim3(256), 0, s, cpart, nchunk, lt, raw_out);

@@ -144,6 +144,16 @@ static size_t footprint(tm_server *S, Request *R)
     return f;
 }
 
+// workspace a request needs when none of its batches is resident
+static size_t standalone_bytes(const tm_server *S, const tm_gauge *G, const tm_tsm_params &P)
+{
+    const Kind kh = kind_of(P.hp), kl = kind_of(P.lp);
+    size_t f = req_bytes(G, P);
+    if (P.n_hp > 0) f += batch_footprint(G, kh, S->slots) + 32 * 256;
+    if (!(kl == kh && P.n_hp > 0)) f += batch_footprint(G, kl, S->slots) + 32 * 256;
+    return f;
+}
+
 static int admit(tm_server *S, Request *R)
 {
     const int lt = R->G->dims[3];
@@ -373,6 +383,15 @@ extern "C" int tm_serve_create(tm_context *ctx, int slots, size_t workspace_budg
     return TM_OK;
 }
 
+extern "C" int tm_serve_footprint(const tm_server *S, const tm_request *req, size_t *bytes)
+{
+    if (!S || !req || !req->gauge || !bytes) return TM_ERR_ARG;
+    int rc = tsm_check(S->ctx, req->gauge, &req->params);
+    if (rc) return rc;
+    *bytes = standalone_bytes(S, req->gauge, req->params);
+    return TM_OK;
+}
+
 extern "C" int tm_serve_submit(tm_server *S, const tm_request *req)
 {
     if (!S || !req || !req->gauge) return TM_ERR_ARG;
@@ -384,12 +403,7 @@ extern "C" int tm_serve_submit(tm_server *S, const tm_request *req)
     R->P = req->params;
     R->t_submit = sclock(S);
     // never admissible: its own buffers plus fresh batches exceed the arena
-    size_t need = req_bytes(R->G, R->P) + 2 * (batch_footprint(R->G, kind_of(R->P.lp), S->slots) + 32 * 256);
-    if (R->P.n_hp > 0)
-        need = req_bytes(R->G, R->P) + batch_footprint(R->G, kind_of(R->P.hp), S->slots) +
-               batch_footprint(R->G, kind_of(R->P.lp), S->slots) + 64 * 256;
-    else
-        need = req_bytes(R->G, R->P) + batch_footprint(R->G, kind_of(R->P.lp), S->slots) + 32 * 256;
+    const size_t need = standalone_bytes(S, R->G, R->P);
     if (need > S->arena.size) {
         delete R;
         return set_err(S->ctx, TM_ERR_NOMEM, "tm_serve_submit: request needs %zu bytes, workspace is %zu", need,

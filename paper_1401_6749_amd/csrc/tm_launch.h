@@ -7,8 +7,8 @@
 
 namespace tmk {
 
-// Dslash with epilogue; sp = storage precision of in/in2/out/p (links of the
-// same precision), x/r in FP64 for sp = P64 else FP32.  Returns -1 on an
+// Dslash with epilogue; sp = storage precision of in/in2/out/p and of x, r
+// in the CG update (links of the same precision).  Returns -1 on an
 // unsupported combination.
 int launch_dslash(int sp, bool dag, int epi, bool in2, const DslashArgs &A, hipStream_t s);
 // plain-epilogue Dslash with Z4-code inputs, uniform (kappa, a):
@@ -51,9 +51,9 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 
 // ---- contractions ----
 int contract_nchunk(const Geom &g);
-// spin matrices of one source into raw_out [9][T][16][2]: s in FP64 or FP32
-// (sps), links FP64, accumulation FP64
-void launch_contract(int sps, const Geom &g, const void *gauge64, const char *s_even, const char *s_odd,
+// spin matrices of one source into raw_out [9][T][16][2]: s and links in FP64
+// or FP32 (sps; gauge must be that precision's link array), accumulation FP64
+void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
                      const uint32_t *codes, double *cpart, double *raw_out, hipStream_t s);
 // raw [n][9][T][16][2] -> ops [n][90][T][2]; gtab: [16][4] (col | phase << 2)
 void launch_project(int n, int lt, const double *raw, double *ops, const int *gtab_host, hipStream_t s);

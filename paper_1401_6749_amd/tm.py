@@ -119,6 +119,7 @@ _sig = {
     "tm_project_loops": (c_int, [c_int, c_int, c_void_p, c_void_p]),
     "tm_serve_create": (c_int, [c_void_p, c_int, c_size_t, ctypes.POINTER(c_void_p)]),
     "tm_serve_submit": (c_int, [c_void_p, ctypes.POINTER(tm_request)]),
+    "tm_serve_footprint": (c_int, [c_void_p, ctypes.POINTER(tm_request), ctypes.POINTER(ctypes.c_size_t)]),
     "tm_serve_poll": (c_int, [c_void_p, ctypes.POINTER(tm_result), c_int]),
     "tm_serve_drain": (c_int, [c_void_p]),
     "tm_result_free": (None, [ctypes.POINTER(tm_result)]),
@@ -345,6 +346,16 @@ def tm_serve_create(ctx, slots=12, workspace_budget=0):
 def tm_serve_submit(srv, gauge, params, tag):
     req = tm_request(gauge, params, int(tag))
     return int(_lib.tm_serve_submit(srv, ctypes.byref(req)))
+
+
+def tm_serve_footprint(srv, gauge, params):
+    """Workspace bytes a request needs from the budget with none of its batches resident."""
+    req = tm_request(gauge, params, 0)
+    n = ctypes.c_size_t(0)
+    rc = _lib.tm_serve_footprint(srv, ctypes.byref(req), ctypes.byref(n))
+    if rc != TM_OK:
+        raise TMError(rc, "tm_serve_footprint")
+    return int(n.value)
 
 
 def tm_serve_poll(srv, max_results=64):

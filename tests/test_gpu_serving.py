@@ -75,8 +75,13 @@ def test_serving_admission_under_small_budget():
     d = (8, 8, 8, 16)
     gs = [GU.load(d, inputs.gauge_field(d, 20 + k)) for k in range(3)]
     P = _req_params(tm, 0.1636, 0.0033, 5, 2, 10)
-    # room for roughly one gauge field's pair of batches at a time
-    srv = tm.tm_serve_create(ctx, slots=4, workspace_budget=48 << 20)
+    # room for one request's output buffers and pair of batches, not two
+    probe = tm.tm_serve_create(ctx, slots=4, workspace_budget=1 << 20)
+    try:
+        need = tm.tm_serve_footprint(probe, gs[0], P)
+    finally:
+        tm.tm_serve_destroy(probe)
+    srv = tm.tm_serve_create(ctx, slots=4, workspace_budget=need * 3 // 2)
     try:
         for k, g in enumerate(gs):
             assert tm.tm_serve_submit(srv, g, P, k) == 0
