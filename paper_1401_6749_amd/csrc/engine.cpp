@@ -64,7 +64,7 @@ int auto_chunk(const tm_gauge *G, Kind k, int S)
 {
     // aim at a few milliseconds of device work between host checks
     const int sp = kind_prec(k);
-    const double lb = sp == P64 ? 96 : sp == P32 ? 48 : 24, sb = sp == P64 ? 192 : sp == P32 ? 96 : 52;
+    const double lb = sp == P64 ? 96 : sp == P32 ? 48 : 36, sb = sp == P64 ? 192 : sp == P32 ? 96 : 52;
     const double bytes_it = (double)G->g.vh * S * (32.0 * lb / 4.0 + 20.0 * sb);
     const double secs = bytes_it / 4.0e12 + 8 * 3e-6;
     int c = (int)(3e-3 / secs);

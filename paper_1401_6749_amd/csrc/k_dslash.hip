@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #ifndef TM_DSLASH_WAVES_F64
 #define TM_DSLASH_WAVES_F64 2
@@ -138,10 +139,18 @@ struct RawHalf {
                       (T)(HalfCodec<P>::dec((uint16_t)(w >> 16)) * sc)};
     }
 };
+template <int SP, class T>
+struct RawSel {
+    using type = Raw<SP, T>;
+};
 template <class T>
-struct Raw<P16, T> : RawHalf<P16, T> {};
+struct RawSel<P16, T> {
+    using type = RawHalf<P16, T>;
+};
 template <class T>
-struct Raw<PBF, T> : RawHalf<PBF, T> {};
+struct RawSel<PBF, T> {
+    using type = RawHalf<PBF, T>;
+};
 
 // Noise neighbour generated from its 4-byte Z4 code: c * eta with c = A^-1
 // per chirality (a prep hop over A^-1 eta_o without any stored spinor).
@@ -160,6 +169,20 @@ struct RawZ4 {
         return cmul(c[k / 6], e);
     }
 };
+
+// the nine packed complex halves (re low, im high) of half-precision link (par, mu) of site i
+__device__ __forceinline__ void load_link_words(__amdgpu_buffer_rsrc_t rs, int vh, int par, int mu, int i,
+                                                uint32_t w[9])
+{
+    const uint32_t base = (uint32_t)(par * 4 + mu) * 36u * (uint32_t)vh;
+#pragma unroll
+    for (int g = 0; g < 2; g++) {
+        const u32x4 q = bld16(rs, (uint32_t)i * 16u, base + (uint32_t)g * 16u * (uint32_t)vh);
+#pragma unroll
+        for (int k = 0; k < 4; k++) w[4 * g + k] = q[k];
+    }
+    w[8] = bld4(rs, (uint32_t)i * 4u, base + 32u * (uint32_t)vh);
+}
 
 // link (par, mu) of site i through the gauge resource
 template <int SP, class T>
@@ -180,14 +203,13 @@ __device__ __forceinline__ void load_link(__amdgpu_buffer_rsrc_t rs, int vh, int
             L.u[(2 * g + 1) / 3][(2 * g + 1) % 3] = cpx<T>{(T)q.z, (T)q.w};
         }
     } else {
+        // all nine entries stored
+        uint32_t w[9];
+        load_link_words(rs, vh, par, mu, i, w);
 #pragma unroll
-        for (int g = 0; g < 3; g++) {
-            const u32x2 q = bld8(rs, (uint32_t)i * 8u, (pm * 3u + g) * (uint32_t)vh * 8u);
-            L.u[(2 * g) / 3][(2 * g) % 3] =
-                cpx<T>{(T)HalfCodec<SP>::dec(q.x & 0xFFFFu), (T)HalfCodec<SP>::dec(q.x >> 16)};
-            L.u[(2 * g + 1) / 3][(2 * g + 1) % 3] =
-                cpx<T>{(T)HalfCodec<SP>::dec(q.y & 0xFFFFu), (T)HalfCodec<SP>::dec(q.y >> 16)};
-        }
+        for (int k = 0; k < 9; k++)
+            L.u[k / 3][k % 3] = cpx<T>{(T)HalfCodec<SP>::dec(w[k] & 0xFFFFu), (T)HalfCodec<SP>::dec(w[k] >> 16)};
+        return;
     }
     rebuild_row2(L);
 }
@@ -251,20 +273,201 @@ __device__ __forceinline__ void raw_setup(RawZ4<T> &z, double den, double a)
     z.c[1] = cpx<T>{(T)den, (T)(a * den)};
 }
 
-// One neighbour: forward x+mu with (1 - g_mu) U_mu(x), or backward x-mu with
-// (1 + g_mu) U_mu(x-mu)^dagger (projectors swapped for DAG).
-template <class T, int SP, int MU, bool FWD, bool DAG, class RawT>
-__device__ __forceinline__ void hop_dir(const DslashArgs &A, const HopRes &R, const Site &s, cpx<T> acc[12],
-                                        double den, double a)
+// ---------------------------------------------------------------------------
+// FP16 hop on packed operands.  A stored spinor component and a stored link
+// entry are each one 32-bit word holding a complex number as two halves
+// (re low, im high).  The spin projection adds two stored components in
+// packed FP16 (one rounding to FP16, the same size as the storage rounding);
+// the colour transport multiplies FP16 link entries by FP16 half-spinor
+// entries with v_dot2_f32_f16, whose two products are exact in FP32 and whose
+// sums are FP32; the neighbour's per-site scale enters in the FP32
+// accumulation.  Signs, conjugation and factors of i are operand modifiers.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b)  // a + b
+{
+    uint32_t d;
+    asm("v_pk_add_f16 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b)  // a - b
+{
+    uint32_t d;
+    asm("v_pk_add_f16 %0, %1, %2 neg_lo:[0,1] neg_hi:[0,1]" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+__device__ __forceinline__ uint32_t pk_sub_i(uint32_t a, uint32_t b)  // a - i b = (a.re + b.im, a.im - b.re)
+{
+    uint32_t d;
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_hi:[0,1]" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+__device__ __forceinline__ uint32_t pk_add_i(uint32_t a, uint32_t b)  // a + i b = (a.re - b.im, a.im + b.re)
+{
+    uint32_t d;
+    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1]" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+// c + a.lo b.lo + a.hi b.hi
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c)
+{
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+// c + a.lo b.lo - a.hi b.hi
+__device__ __forceinline__ float dot2_nh(uint32_t a, uint32_t b, float c)
+{
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, %3 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+// the same with c = 0 (inline constant, no zeroed register)
+__device__ __forceinline__ float dot2_z(uint32_t a, uint32_t b)
+{
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+__device__ __forceinline__ float dot2_nh_z(uint32_t a, uint32_t b)
+{
+    float d;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+__device__ __forceinline__ uint32_t swap16(uint32_t a) { return __builtin_amdgcn_alignbit(a, a, 16); }
+
+// packed half spinor of colour c for the projector (1 + S g_mu), from stored words p[k], k = 3*spin + colour
+template <int MU, int S>
+__device__ __forceinline__ void project_pk(const uint32_t p[12], int c, uint32_t &h0, uint32_t &h1)
+{
+    const uint32_t p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+    if (MU == 0) {
+        h0 = S > 0 ? pk_sub_i(p0, p3) : pk_add_i(p0, p3);
+        h1 = S > 0 ? pk_sub_i(p1, p2) : pk_add_i(p1, p2);
+    } else if (MU == 1) {
+        h0 = S > 0 ? pk_sub(p0, p3) : pk_add(p0, p3);
+        h1 = S > 0 ? pk_add(p1, p2) : pk_sub(p1, p2);
+    } else if (MU == 2) {
+        h0 = S > 0 ? pk_sub_i(p0, p2) : pk_add_i(p0, p2);
+        h1 = S > 0 ? pk_add_i(p1, p3) : pk_sub_i(p1, p3);
+    } else {
+        h0 = S > 0 ? pk_add(p0, p2) : pk_sub(p0, p2);
+        h1 = S > 0 ? pk_add(p1, p3) : pk_sub(p1, p3);
+    }
+}
+
+// w = U h (FWD) or U^dagger h from packed link words u[3*row+col] and packed h
+template <bool FWD>
+__device__ __forceinline__ void transport_pk(const uint32_t u[9], const uint32_t h[3], const uint32_t hs[3],
+                                             float wr[3], float wi[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        float re, im;
+        if (FWD) {  // U[a][b] h[b]: re = u.re h.re - u.im h.im, im = u.re h.im + u.im h.re
+            re = dot2_nh_z(u[3 * a], h[0]);
+            im = dot2_z(u[3 * a], hs[0]);
+#pragma unroll
+            for (int b = 1; b < 3; b++) {
+                re = dot2_nh(u[3 * a + b], h[b], re);
+                im = dot2(u[3 * a + b], hs[b], im);
+            }
+        } else {  // conj(U[b][a]) h[b]: re = u.re h.re + u.im h.im, im = u.re h.im - u.im h.re
+            re = dot2_z(u[a], h[0]);
+            im = dot2_nh_z(u[a], hs[0]);
+#pragma unroll
+            for (int b = 1; b < 3; b++) {
+                re = dot2(u[3 * b + a], h[b], re);
+                im = dot2_nh(u[3 * b + a], hs[b], im);
+            }
+        }
+        wr[a] = re;
+        wi[a] = im;
+    }
+}
+
+// acc += sc * (the four spin rows rebuilt from w0 = (wr0, wi0), w1 = (wr1, wi1)) as in accum
+template <int MU, int S>
+__device__ __forceinline__ void accum_pk(cpx<float> acc[12], const float wr0[3], const float wi0[3],
+                                         const float wr1[3], const float wi1[3], float sc)
+{
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        acc[c].re = fmaf(sc, wr0[c], acc[c].re);
+        acc[c].im = fmaf(sc, wi0[c], acc[c].im);
+        acc[3 + c].re = fmaf(sc, wr1[c], acc[3 + c].re);
+        acc[3 + c].im = fmaf(sc, wi1[c], acc[3 + c].im);
+        if (MU == 0) {  // rows 2,3 = iS w1, iS w0
+            const float s = S > 0 ? sc : -sc;
+            acc[6 + c].re = fmaf(-s, wi1[c], acc[6 + c].re);
+            acc[6 + c].im = fmaf(s, wr1[c], acc[6 + c].im);
+            acc[9 + c].re = fmaf(-s, wi0[c], acc[9 + c].re);
+            acc[9 + c].im = fmaf(s, wr0[c], acc[9 + c].im);
+        } else if (MU == 1) {  // S w1, -S w0
+            const float s = S > 0 ? sc : -sc;
+            acc[6 + c].re = fmaf(s, wr1[c], acc[6 + c].re);
+            acc[6 + c].im = fmaf(s, wi1[c], acc[6 + c].im);
+            acc[9 + c].re = fmaf(-s, wr0[c], acc[9 + c].re);
+            acc[9 + c].im = fmaf(-s, wi0[c], acc[9 + c].im);
+        } else if (MU == 2) {  // iS w0, -iS w1
+            const float s = S > 0 ? sc : -sc;
+            acc[6 + c].re = fmaf(-s, wi0[c], acc[6 + c].re);
+            acc[6 + c].im = fmaf(s, wr0[c], acc[6 + c].im);
+            acc[9 + c].re = fmaf(s, wi1[c], acc[9 + c].re);
+            acc[9 + c].im = fmaf(-s, wr1[c], acc[9 + c].im);
+        } else {  // S w0, S w1
+            const float s = S > 0 ? sc : -sc;
+            acc[6 + c].re = fmaf(s, wr0[c], acc[6 + c].re);
+            acc[6 + c].im = fmaf(s, wi0[c], acc[6 + c].im);
+            acc[9 + c].re = fmaf(s, wr1[c], acc[9 + c].re);
+            acc[9 + c].im = fmaf(s, wi1[c], acc[9 + c].im);
+        }
+    }
+}
+
+// One FP16 neighbour n of site s on packed operands (see above); raw holds
+// the neighbour's stored words.
+template <int MU, bool FWD, bool DAG>
+__device__ __forceinline__ void hop_compute_pk(const DslashArgs &A, __amdgpu_buffer_rsrc_t gauge, const Site &s, int n,
+                                               const RawHalf<P16, float> &raw, cpx<float> acc[12])
 {
     const int vh = A.g.vh;
     constexpr int S = (FWD != DAG) ? -1 : 1;
-    const int n = nbr<MU, FWD ? 1 : -1>(A.g, s);
-    RawT raw;
-    raw_setup(raw, den, a);
-    raw.load(R.in, R.lane, vh, n);
+    uint32_t p[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) p[k] = raw.q[k >> 2][k & 3];
+    float sc = raw.sc;
+    uint32_t u[9];
+    load_link_words(gauge, vh, FWD ? A.out_par : 1 - A.out_par, MU, FWD ? s.cb : n, u);
+    if (MU == 3 && A.g.tbc < 0 && s.t == (FWD ? A.g.L[3] - 1 : 0)) sc = -sc;
+    uint32_t h0[3], h1[3], h0s[3], h1s[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        project_pk<MU, S>(p, c, h0[c], h1[c]);
+        h0s[c] = swap16(h0[c]);
+        h1s[c] = swap16(h1[c]);
+    }
+    float wr0[3], wi0[3], wr1[3], wi1[3];
+    transport_pk<FWD>(u, h0, h0s, wr0, wi0);
+    transport_pk<FWD>(u, h1, h1s, wr1, wi1);
+    accum_pk<MU, S>(acc, wr0, wi0, wr1, wi1, sc);
+}
+
+// One neighbour n of site s from its loaded storage form raw: forward x+mu
+// with (1 - g_mu) U_mu(x), or backward x-mu with (1 + g_mu) U_mu(x-mu)^dagger
+// (projectors swapped for DAG).
+template <class T, int SP, int MU, bool FWD, bool DAG, class RawT>
+__device__ __forceinline__ void hop_compute(const DslashArgs &A, __amdgpu_buffer_rsrc_t gauge, const Site &s, int n,
+                                            const RawT &raw, cpx<T> acc[12])
+{
+    if constexpr (SP == P16 && std::is_same<RawT, RawHalf<P16, float>>::value) {
+        hop_compute_pk<MU, FWD, DAG>(A, gauge, s, n, raw, acc);
+        return;
+    }
+    const int vh = A.g.vh;
+    constexpr int S = (FWD != DAG) ? -1 : 1;
     Link<T> L;
-    load_link<SP, T>(R.gauge, vh, FWD ? A.out_par : 1 - A.out_par, MU, FWD ? s.cb : n, L);
+    load_link<SP, T>(gauge, vh, FWD ? A.out_par : 1 - A.out_par, MU, FWD ? s.cb : n, L);
     cpx<T> w[6];
     transport<T, MU, S, FWD>(L, raw, w);
     if (MU == 3 && A.g.tbc < 0 && s.t == (FWD ? A.g.L[3] - 1 : 0)) {
@@ -272,6 +475,18 @@ __device__ __forceinline__ void hop_dir(const DslashArgs &A, const HopRes &R, co
         for (int k = 0; k < 6; k++) w[k] = cpx<T>{-w[k].re, -w[k].im};
     }
     accum<T, MU, S>(acc, w);
+}
+
+// One neighbour read from the input resource.
+template <class T, int SP, int MU, bool FWD, bool DAG, class RawT>
+__device__ __forceinline__ void hop_dir(const DslashArgs &A, const HopRes &R, const Site &s, cpx<T> acc[12],
+                                        double den, double a)
+{
+    const int n = nbr<MU, FWD ? 1 : -1>(A.g, s);
+    RawT raw;
+    raw_setup(raw, den, a);
+    raw.load(R.in, R.lane, A.g.vh, n);
+    hop_compute<T, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
 }
 
 // The eight neighbours as a runtime loop of uniform branches: each stage is
@@ -331,6 +546,72 @@ constexpr int dslash_waves()
     return SP == P64 ? TM_DSLASH_WAVES_F64 : SP == P32 ? TM_DSLASH_WAVES_F32 : TM_DSLASH_WAVES_F16;
 }
 
+// Site-local epilogue of output site cb of slot: out = P in2 + Q hop with the
+// CG update / residual variants; returns the site's contribution to the
+// slot's reduction (0 for EPI_PLAIN).
+template <int SP, int EPI, bool IN2, int SRC>
+__device__ __forceinline__ double epilogue(const DslashArgs &A, int slot, int cb, const cpx<typename Real<SP>::T> acc[12],
+                                           double kappa, double a, double alpha)
+{
+    using T = typename Real<SP>::T;
+    constexpr int XR = SP;  // x and r share the storage precision of the Dslash operands
+    const int vh = A.g.vh;
+    double part = 0.0;
+    cpx<T> P[2], Q[2];
+    coefs<T>(A.coef, kappa, a, P, Q);
+    cpx<T> v[12];
+    if (IN2) {
+        cpx<T> y[12];
+        if constexpr (SRC & 2) {
+            const uint32_t c = A.codes[(size_t)slot * A.codes_slot / 4 + (size_t)A.out_par * vh + cb];
+            const T h = (T)0.70710678118654752440;
+#pragma unroll
+            for (int k = 0; k < 12; k++)
+                y[k] = cpx<T>{((c >> (2 * k)) & 1u) ? -h : h, ((c >> (2 * k + 1)) & 1u) ? -h : h};
+        } else {
+            SpinorIO<SP>::load(A.in2 + (size_t)slot * A.in2_slot, vh, cb, y);
+        }
+#pragma unroll
+        for (int k = 0; k < 12; k++) v[k] = cmul(P[k / 6], y[k]) + cmul(Q[k / 6], acc[k]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; k++) v[k] = cmul(Q[k / 6], acc[k]);
+    }
+    if (EPI == EPI_PLAIN || EPI == EPI_NORM) {
+        SpinorIO<SP>::store(A.out + (size_t)slot * A.out_slot, vh, cb, v);
+        if (EPI == EPI_NORM) {
+#pragma unroll
+            for (int k = 0; k < 12; k++) part += (double)norm2(v[k]);
+        }
+    } else if (EPI == EPI_CGUPD) {
+        cpx<T> p[12], x[12], rr[12];
+        SpinorIO<SP>::load(A.p + (size_t)slot * A.p_slot, vh, cb, p);
+        char *xs = A.x + (size_t)slot * A.xr_slot;
+        char *rs = A.r + (size_t)slot * A.xr_slot;
+        SpinorIO<XR>::load(xs, vh, cb, x);
+        SpinorIO<XR>::load(rs, vh, cb, rr);
+        const T al = (T)alpha;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            x[k] = x[k] + cscale(al, p[k]);
+            rr[k] = rr[k] - cscale(al, v[k]);
+            part += (double)norm2(rr[k]);
+        }
+        SpinorIO<XR>::store(xs, vh, cb, x);
+        SpinorIO<XR>::store(rs, vh, cb, rr);
+    } else {  // EPI_RESID (FP64 only)
+        cpx<T> b[12];
+        SpinorIO<P64>::load(A.b + (size_t)slot * A.b_slot, vh, cb, b);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            v[k] = b[k] - v[k];
+            part += (double)norm2(v[k]);
+        }
+        SpinorIO<SP>::store(A.out + (size_t)slot * A.out_slot, vh, cb, v);
+    }
+    return part;
+}
+
 // Thread mapping: a block holds BLOCK/R sites x R right-hand sides ("slots")
 // of one slot group, lane = site * R + r, so the R lanes of a site sit in the
 // same wave and their link loads hit the same addresses: each link is
@@ -344,12 +625,11 @@ template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, int R, int SRC = 0>
 __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const DslashArgs A)
 {
     using T = typename Real<SP>::T;
-    constexpr int XR = SP;  // x and r share the storage precision of the Dslash operands
     constexpr int SPB = BLOCK / R;  // sites per block
     __shared__ double red[EPI == EPI_PLAIN ? 1 : BLOCK];
     const int ngroups = (A.nslot + R - 1) / R;
     int sb, grp;
-    if (!map_block(A.nblk_site, ngroups, A.swz, sb, grp)) return;
+    if (!map_block(A.nblk_site, ngroups, A.swz, sb, grp, A.gouter != 0)) return;
     const int r = threadIdx.x % R, sl = threadIdx.x / R;
     const int slot = grp * R + r;
     bool live = slot < A.nslot;
@@ -404,60 +684,9 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
         } else {
             res.in = mkrsrc(A.in + (size_t)grp * R * A.in_slot, A.in_span);
             res.lane = (uint32_t)r * (uint32_t)A.in_slot;
-            hop_all<T, SP, DAG, Raw<SP, T>>(A, res, s, acc, 0.0, 0.0);
+            hop_all<T, SP, DAG, typename RawSel<SP, T>::type>(A, res, s, acc, 0.0, 0.0);
         }
-        cpx<T> P[2], Q[2];
-        coefs<T>(A.coef, kappa, a, P, Q);
-        cpx<T> v[12];
-        if (IN2) {
-            cpx<T> y[12];
-            if constexpr (SRC & 2) {
-                const uint32_t c = A.codes[(size_t)slot * A.codes_slot / 4 + (size_t)A.out_par * vh + cb];
-                const T h = (T)0.70710678118654752440;
-#pragma unroll
-                for (int k = 0; k < 12; k++)
-                    y[k] = cpx<T>{((c >> (2 * k)) & 1u) ? -h : h, ((c >> (2 * k + 1)) & 1u) ? -h : h};
-            } else {
-                SpinorIO<SP>::load(A.in2 + (size_t)slot * A.in2_slot, vh, cb, y);
-            }
-#pragma unroll
-            for (int k = 0; k < 12; k++) v[k] = cmul(P[k / 6], y[k]) + cmul(Q[k / 6], acc[k]);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 12; k++) v[k] = cmul(Q[k / 6], acc[k]);
-        }
-        if (EPI == EPI_PLAIN || EPI == EPI_NORM) {
-            SpinorIO<SP>::store(A.out + (size_t)slot * A.out_slot, vh, cb, v);
-            if (EPI == EPI_NORM) {
-#pragma unroll
-                for (int k = 0; k < 12; k++) part += (double)norm2(v[k]);
-            }
-        } else if (EPI == EPI_CGUPD) {
-            cpx<T> p[12], x[12], rr[12];
-            SpinorIO<SP>::load(A.p + (size_t)slot * A.p_slot, vh, cb, p);
-            char *xs = A.x + (size_t)slot * A.xr_slot;
-            char *rs = A.r + (size_t)slot * A.xr_slot;
-            SpinorIO<XR>::load(xs, vh, cb, x);
-            SpinorIO<XR>::load(rs, vh, cb, rr);
-            const T al = (T)alpha;
-#pragma unroll
-            for (int k = 0; k < 12; k++) {
-                x[k] = x[k] + cscale(al, p[k]);
-                rr[k] = rr[k] - cscale(al, v[k]);
-                part += (double)norm2(rr[k]);
-            }
-            SpinorIO<XR>::store(xs, vh, cb, x);
-            SpinorIO<XR>::store(rs, vh, cb, rr);
-        } else {  // EPI_RESID (FP64 only)
-            cpx<T> b[12];
-            SpinorIO<P64>::load(A.b + (size_t)slot * A.b_slot, vh, cb, b);
-#pragma unroll
-            for (int k = 0; k < 12; k++) {
-                v[k] = b[k] - v[k];
-                part += (double)norm2(v[k]);
-            }
-            SpinorIO<SP>::store(A.out + (size_t)slot * A.out_slot, vh, cb, v);
-        }
+        part = epilogue<SP, EPI, IN2, SRC>(A, slot, cb, acc, kappa, a, alpha);
     }
     if constexpr (EPI != EPI_PLAIN) {
         // tile sums: wave w reduces (slot r_w, tile t_w) of this block
@@ -472,6 +701,159 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
         const int tile = (cb - sl) / 64 + tw_;
         if (lane == 0 && sw < A.nslot && tile < A.ntile) A.partial[(size_t)sw * A.ntile + tile] = v;
     }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Timeslice walk through LDS (FP32 and half storage, one slot per block).
+//
+// A block owns a chunk of WSPB consecutive sites of one timeslice (one site
+// per thread) for one right-hand side and walks tw consecutive timeslices.
+// Every input site the walk touches is read from HBM (or L2) once: at each
+// step the thread loads its own site of timeslice t+1, which is at once its
+// forward t neighbour; the block stages that timeslice in LDS for the next
+// step's x, y (and, for small planes, z) neighbours, and the other LDS buffer
+// still holds timeslice t-1, the backward t neighbour.  Only neighbours
+// outside the chunk (the z planes above and below, and y rows at the chunk's
+// edges) are read from global memory, where the blocks working on those
+// chunks have just fetched them into L2.  Two LDS buffers, one barrier per
+// step.  The arithmetic per site is that of k_dslash, in the same order, so
+// both give the same bits.
+// ---------------------------------------------------------------------------
+constexpr int WSPB = 256;
+
+template <int SP>
+struct WalkBuf;
+template <>
+struct WalkBuf<P32> {
+    u32x4 q[2][6][WSPB];
+    __device__ __forceinline__ void get(int b, int d, Raw<P32, float> &r) const
+    {
+#pragma unroll
+        for (int g = 0; g < 6; g++) r.q[g] = as_f4(q[b][g][d]);
+    }
+    __device__ __forceinline__ void put(int b, int d, const Raw<P32, float> &r)
+    {
+#pragma unroll
+        for (int g = 0; g < 6; g++) __builtin_memcpy(&q[b][g][d], &r.q[g], 16);
+    }
+};
+template <int SP>
+struct WalkBufHalf {
+    u32x4 q[2][3][WSPB];
+    float sc[2][WSPB];
+    __device__ __forceinline__ void get(int b, int d, RawHalf<SP, float> &r) const
+    {
+#pragma unroll
+        for (int g = 0; g < 3; g++) r.q[g] = q[b][g][d];
+        r.sc = sc[b][d];
+    }
+    __device__ __forceinline__ void put(int b, int d, const RawHalf<SP, float> &r)
+    {
+#pragma unroll
+        for (int g = 0; g < 3; g++) q[b][g][d] = r.q[g];
+        sc[b][d] = r.sc;
+    }
+};
+template <>
+struct WalkBuf<P16> : WalkBufHalf<P16> {};
+template <>
+struct WalkBuf<PBF> : WalkBufHalf<PBF> {};
+
+struct WalkPos {
+    int base;  // cb of the chunk's first site in the current timeslice
+    int buf;   // LDS buffer holding the current timeslice
+};
+
+template <int SP, int MU, bool FWD, bool DAG>
+__device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, const Site &s, const WalkBuf<SP> &W,
+                                         const WalkPos &w, const typename RawSel<SP, float>::type &nxt,
+                                         cpx<float> acc[12])
+{
+    using RawT = typename RawSel<SP, float>::type;
+    const int n = nbr<MU, FWD ? 1 : -1>(A.g, s);
+    if constexpr (MU == 3) {
+        if constexpr (FWD) {
+            hop_compute<float, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, nxt, acc);
+        } else {
+            RawT raw;
+            W.get(w.buf ^ 1, threadIdx.x, raw);
+            hop_compute<float, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
+        }
+    } else {
+        RawT raw;
+        const uint32_t d = (uint32_t)(n - w.base);
+        if (d < (uint32_t)WSPB) W.get(w.buf, (int)d, raw);
+        else raw.load(R.in, 0, A.g.vh, n);
+        hop_compute<float, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
+    }
+}
+
+template <int SP, bool DAG, int EPI, bool IN2, bool SLOT>
+__global__ __launch_bounds__(WSPB, dslash_waves<SP>()) void k_dslash_walk(const DslashArgs A)
+{
+    using RawT = typename RawSel<SP, float>::type;
+    __shared__ WalkBuf<SP> W;
+    int sb, slot;
+    if (!map_block(A.nblk_site, A.nslot, A.swz, sb, slot, A.gouter != 0)) return;
+    double kappa = A.kappa_u, a = A.a_u, alpha = 0;
+    if constexpr (SLOT) {
+        const SlotState &st = A.st[slot];
+        if (st.status != ST_RUNNING) return;  // uniform over the block
+        kappa = st.kappa;
+        a = st.a;
+        alpha = st.alpha;
+    }
+    const Geom &g = A.g;
+    const int vh = g.vh, lt = g.L[3], tw = A.twalk;
+    const int chunks = g.v3h / WSPB;
+    const int tb = sb / chunks, o = (sb - tb * chunks) * WSPB + (int)threadIdx.x;
+    const int t0 = tb * tw;
+    HopRes R;
+    R.gauge = mkrsrc(A.gauge, A.gauge_span);
+    R.in = mkrsrc(A.in + (size_t)slot * A.in_slot, A.in_span);
+    R.lane = 0;
+    {
+        RawT r0, r1;
+        r0.load(R.in, 0, vh, ((t0 + lt - 1) % lt) * g.st + o);
+        r1.load(R.in, 0, vh, t0 * g.st + o);
+        W.put(1, threadIdx.x, r0);
+        W.put(0, threadIdx.x, r1);
+    }
+    __syncthreads();
+    for (int k = 0; k < tw; k++) {
+        const int t = t0 + k;
+        const int cb = t * g.st + o;
+        RawT nxt;
+        nxt.load(R.in, 0, vh, ((t + 1) % lt) * g.st + o);
+        const WalkPos w{t * g.st + (o - (int)threadIdx.x), k & 1};
+        const Site s = site_of(g, cb, A.out_par);
+        cpx<float> acc[12];
+#pragma unroll
+        for (int q = 0; q < 12; q++) acc[q] = cpx<float>{0.f, 0.f};
+#pragma unroll 1
+        for (int d = 0; d < 8; d++) {
+            switch (__builtin_amdgcn_readfirstlane(d)) {
+            case 0: walk_dir<SP, 0, true, DAG>(A, R, s, W, w, nxt, acc); break;
+            case 1: walk_dir<SP, 0, false, DAG>(A, R, s, W, w, nxt, acc); break;
+            case 2: walk_dir<SP, 1, true, DAG>(A, R, s, W, w, nxt, acc); break;
+            case 3: walk_dir<SP, 1, false, DAG>(A, R, s, W, w, nxt, acc); break;
+            case 4: walk_dir<SP, 2, true, DAG>(A, R, s, W, w, nxt, acc); break;
+            case 5: walk_dir<SP, 2, false, DAG>(A, R, s, W, w, nxt, acc); break;
+            case 6: walk_dir<SP, 3, true, DAG>(A, R, s, W, w, nxt, acc); break;
+            default: walk_dir<SP, 3, false, DAG>(A, R, s, W, w, nxt, acc); break;
+            }
+        }
+        const double part = epilogue<SP, EPI, IN2, 0>(A, slot, cb, acc, kappa, a, alpha);
+        if constexpr (EPI != EPI_PLAIN) {
+            // one wave = one 64-site reduction tile
+            const double v = wave_sum(part);
+            if ((threadIdx.x & 63) == 0) A.partial[(size_t)slot * A.ntile + cb / TILE] = v;
+        }
+        // timeslice t+1 replaces t-1 (read by this thread only) for the next step
+        W.put(w.buf ^ 1, threadIdx.x, nxt);
+        __syncthreads();
     }
 }
 
@@ -497,23 +879,73 @@ inline int dslash_twalk()
     return tw;
 }
 
-// lanes per site: one per slot up to 4
-inline int lanes_per_site(int nslot) { return nslot >= 3 ? 4 : nslot; }
+// integer tuning knob from the environment (read once)
+inline int env_knob(const char *name, int dflt)
+{
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
+// lanes per site: one per slot up to 4 (TM_DSLASH_R caps it)
+inline int lanes_per_site(int nslot)
+{
+    static const int cap = std::max(1, std::min(4, env_knob("TM_DSLASH_R", 4)));
+    int r = nslot >= 3 ? 4 : nslot;
+    while (r > cap) r /= 2;
+    return r;
+}
+
+// timeslices per block of the LDS walk (TM_LDS_TWALK; TM_LDS_WALK=0 disables the walk)
+inline int lds_twalk()
+{
+    static const int tw = env_knob("TM_LDS_WALK", 1) ? std::max(1, env_knob("TM_LDS_TWALK", 8)) : 0;
+    return tw;
+}
+
+template <int SP, bool DAG, int EPI, bool IN2>
+static bool launch_walk(DslashArgs A, hipStream_t s)
+{
+    if constexpr (SP == P64) {
+        return false;
+    } else {
+        int tw = lds_twalk();
+        const uint64_t field = (uint64_t)A.g.vh * (SP == P32 ? 96 : 52);
+        if (tw < 1 || A.g.v3h % WSPB != 0 || field >= (1ull << 32)) return false;
+        while (A.g.L[3] % tw) tw--;
+        A.twalk = tw;
+        A.in_span = (uint32_t)field;
+        A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P32 ? 48 : 36), 0xFFFFFFFFull);
+        static const int gouter = env_knob("TM_GROUP_OUTER", 0);
+        A.gouter = gouter;
+        A.nblk_site = A.g.vh / WSPB / tw;
+        A.ntile = ntile_of(A.g);
+        const int total = A.nblk_site * A.nslot;
+        const int grid = A.swz ? 8 * ((total + 7) / 8) : total;
+        if (A.st)
+            hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, true>), dim3(grid), dim3(WSPB), 0, s, A);
+        else
+            hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, false>), dim3(grid), dim3(WSPB), 0, s, A);
+        return true;
+    }
+}
 
 template <int SP, bool DAG, int EPI, bool IN2>
 static void launch_t(DslashArgs A, hipStream_t s)
 {
+    if (launch_walk<SP, DAG, EPI, IN2>(A, s)) return;
     int R = lanes_per_site(A.nslot);
     // 32-bit buffer offsets: the R input fields of a group must span < 4 GiB
     const uint64_t field = (uint64_t)A.g.vh * (SP == P64 ? 192 : SP == P32 ? 96 : 52);
     if (R > 1 && ((uint64_t)(R - 1) * A.in_slot + field >= (1ull << 32) || A.in_slot % 16)) R = 1;
     A.in_span = (uint32_t)std::min<uint64_t>((uint64_t)(R - 1) * A.in_slot + field, 0xFFFFFFFFull);
-    A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : SP == P32 ? 48 : 24),
+    A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : SP == P32 ? 48 : 36),
                                                 0xFFFFFFFFull);
     const int spb = BLOCK / R;
     int tw = dslash_twalk();
     if (tw > 1 && (A.g.v3h % spb != 0 || A.g.L[3] % tw != 0)) tw = 1;
     A.twalk = tw;
+    static const int gouter = env_knob("TM_GROUP_OUTER", 0);
+    A.gouter = gouter;
     A.nblk_site = tw > 1 ? A.g.vh / spb / tw : (A.g.vh + spb - 1) / spb;
     A.ntile = ntile_of(A.g);
     if (R == 1) launch_r<SP, DAG, EPI, IN2, 1>(A, s);
@@ -546,6 +978,7 @@ template <int SP, int SRC>
 static void launch_src(DslashArgs A, hipStream_t s)
 {
     A.twalk = 1;
+    A.gouter = 0;
     A.nblk_site = (A.g.vh + BLOCK - 1) / BLOCK;
     A.ntile = ntile_of(A.g);
     A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : 48), 0xFFFFFFFFull);

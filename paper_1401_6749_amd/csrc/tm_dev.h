@@ -245,13 +245,17 @@ template <>
 struct SpinorIO<PBF> : SpinorHalfIO<PBF> {};
 
 __host__ __device__ constexpr size_t spinor_site_bytes(int p) { return p == P64 ? 192 : p == P32 ? 96 : 52; }
-__host__ __device__ constexpr size_t link_bytes(int p) { return p == P64 ? 96 : p == P32 ? 48 : 24; }
+__host__ __device__ constexpr size_t link_bytes(int p) { return p == P64 ? 96 : p == P32 ? 48 : 36; }
 
 // ---------------------------------------------------------------------------
-// Links: first two rows (12 reals) per link, third row rebuilt as the
-// complex conjugate of the cross product of the first two (det U = 1).
+// Links.  P64/P32: first two rows (12 reals) per link, third row rebuilt as
+// the complex conjugate of the cross product of the first two (det U = 1).
+// P16/PBF: all nine entries (18 halves), so the half-precision hop needs no
+// arithmetic to rebuild a row.
 // Per precision the array is [parity 2][mu 4][group][Vh]:
-//   P64: 6 double2 groups (entries 3*row+col), P32: 3 float4, P16/PBF: 3 x 4 halves
+//   P64: 6 double2 groups (entries 3*row+col), P32: 3 float4 (entries 2g, 2g+1),
+//   P16/PBF: 2 groups of 4 packed complex halves (entries 4g..4g+3) then entry 8
+//   (one packed complex) per site
 // ---------------------------------------------------------------------------
 template <class T>
 struct Link {
@@ -308,16 +312,20 @@ struct LinkHalfIO {
     template <class T>
     __device__ static __forceinline__ void load(const void *G, int vh, int par, int mu, int i, Link<T> &L)
     {
-        const uint2 *p = (const uint2 *)G + (size_t)(par * 4 + mu) * 3 * vh;
+        const char *base = (const char *)G + (size_t)(par * 4 + mu) * 36 * vh;
+        uint32_t w[9];
 #pragma unroll
-        for (int g = 0; g < 3; g++) {
-            uint2 q = p[(size_t)g * vh + i];
-            L.u[(2 * g) / 3][(2 * g) % 3] =
-                cpx<T>{(T)HalfCodec<P>::dec(q.x & 0xFFFFu), (T)HalfCodec<P>::dec(q.x >> 16)};
-            L.u[(2 * g + 1) / 3][(2 * g + 1) % 3] =
-                cpx<T>{(T)HalfCodec<P>::dec(q.y & 0xFFFFu), (T)HalfCodec<P>::dec(q.y >> 16)};
+        for (int g = 0; g < 2; g++) {
+            const uint4 q = ((const uint4 *)base)[(size_t)g * vh + i];
+            w[4 * g] = q.x;
+            w[4 * g + 1] = q.y;
+            w[4 * g + 2] = q.z;
+            w[4 * g + 3] = q.w;
         }
-        rebuild_row2(L);
+        w[8] = ((const uint32_t *)(base + (size_t)32 * vh))[i];
+#pragma unroll
+        for (int k = 0; k < 9; k++)
+            L.u[k / 3][k % 3] = cpx<T>{(T)HalfCodec<P>::dec(w[k] & 0xFFFFu), (T)HalfCodec<P>::dec(w[k] >> 16)};
     }
 };
 template <>
@@ -409,7 +417,9 @@ __device__ __forceinline__ double block_sum(double v, double *lds /* NT/64 doubl
 // the 8 XCDs in turn; remap so that each XCD walks a contiguous range of
 // (site block, slot) pairs, slots of the same site block back to back, so
 // the links and neighbour spinors of a range stay in that XCD's L2.
-__device__ __forceinline__ bool map_block(int nblk_site, int nslot, int swz, int &sblk, int &slot)
+// gouter: slot (group) index slowest instead of fastest
+__device__ __forceinline__ bool map_block(int nblk_site, int nslot, int swz, int &sblk, int &slot,
+                                          bool gouter = false)
 {
     const int total = nblk_site * nslot;
     const int bid = blockIdx.x;
@@ -419,8 +429,13 @@ __device__ __forceinline__ bool map_block(int nblk_site, int nslot, int swz, int
         l = (bid & 7) * per + (bid >> 3);
     }
     if (l >= total) return false;
-    sblk = l / nslot;
-    slot = l - sblk * nslot;
+    if (gouter) {
+        slot = l / nblk_site;
+        sblk = l - slot * nblk_site;
+    } else {
+        sblk = l / nslot;
+        slot = l - sblk * nslot;
+    }
     return true;
 }
 

@@ -125,6 +125,7 @@ struct DslashArgs {
     int ntile;                  // 64-site reduction tiles per slot
     uint32_t in_span, gauge_span;  // bytes reachable through the buffer resources (set by the launcher)
     int twalk;                     // timeslices walked per block (set by the launcher)
+    int gouter;                    // slot groups slowest in the block order (set by the launcher)
     double *partial;            // [nslot][ntile]
     // EPI_CGUPD
     char *x, *r;
