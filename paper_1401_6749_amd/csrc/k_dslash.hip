@@ -549,7 +549,7 @@ constexpr int dslash_waves()
 // Site-local epilogue of output site cb of slot: out = P in2 + Q hop with the
 // CG update / residual variants; returns the site's contribution to the
 // slot's reduction (0 for EPI_PLAIN).
-template <int SP, int EPI, bool IN2, int SRC>
+template <int SP, int EPI, bool IN2, int SRC, bool NT = false>
 __device__ __forceinline__ double epilogue(const DslashArgs &A, int slot, int cb, const cpx<typename Real<SP>::T> acc[12],
                                            double kappa, double a, double alpha)
 {
@@ -578,7 +578,7 @@ __device__ __forceinline__ double epilogue(const DslashArgs &A, int slot, int cb
         for (int k = 0; k < 12; k++) v[k] = cmul(Q[k / 6], acc[k]);
     }
     if (EPI == EPI_PLAIN || EPI == EPI_NORM) {
-        SpinorIO<SP>::store(A.out + (size_t)slot * A.out_slot, vh, cb, v);
+        SpinorIO<SP>::template store<T, NT>(A.out + (size_t)slot * A.out_slot, vh, cb, v);
         if (EPI == EPI_NORM) {
 #pragma unroll
             for (int k = 0; k < 12; k++) part += (double)norm2(v[k]);
@@ -607,7 +607,7 @@ __device__ __forceinline__ double epilogue(const DslashArgs &A, int slot, int cb
             v[k] = b[k] - v[k];
             part += (double)norm2(v[k]);
         }
-        SpinorIO<SP>::store(A.out + (size_t)slot * A.out_slot, vh, cb, v);
+        SpinorIO<SP>::template store<T, NT>(A.out + (size_t)slot * A.out_slot, vh, cb, v);
     }
     return part;
 }
@@ -708,8 +708,9 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
 // ---------------------------------------------------------------------------
 // Timeslice walk through LDS (FP32 and half storage, one slot per block).
 //
-// A block owns a chunk of WSPB consecutive sites of one timeslice (one site
-// per thread) for one right-hand side and walks tw consecutive timeslices.
+// A block owns a chunk of one timeslice, cy rows (y) x cz planes (z) of full
+// x rows, one site per thread (at most WSPB), for one right-hand side and
+// walks tw consecutive timeslices.
 // Every input site the walk touches is read from HBM (or L2) once: at each
 // step the thread loads its own site of timeslice t+1, which is at once its
 // forward t neighbour; the block stages that timeslice in LDS for the next
@@ -718,8 +719,9 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
 // outside the chunk (the z planes above and below, and y rows at the chunk's
 // edges) are read from global memory, where the blocks working on those
 // chunks have just fetched them into L2.  Two LDS buffers, one barrier per
-// step.  The arithmetic per site is that of k_dslash, in the same order, so
-// both give the same bits.
+// step.  The chunk shape is picked on the host to minimise the halo; each
+// 64-thread wave covers one 64-site reduction tile.  The arithmetic per site
+// is that of k_dslash, in the same order, so both give the same bits.
 // ---------------------------------------------------------------------------
 constexpr int WSPB = 256;
 
@@ -762,8 +764,8 @@ template <>
 struct WalkBuf<PBF> : WalkBufHalf<PBF> {};
 
 struct WalkPos {
-    int base;  // cb of the chunk's first site in the current timeslice
-    int buf;   // LDS buffer holding the current timeslice
+    int buf;     // LDS buffer holding the current timeslice
+    int yy, zz;  // the thread's row and plane within the chunk
 };
 
 template <int SP, int MU, bool FWD, bool DAG>
@@ -783,14 +785,25 @@ __device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, c
         }
     } else {
         RawT raw;
-        const uint32_t d = (uint32_t)(n - w.base);
-        if (d < (uint32_t)WSPB) W.get(w.buf, (int)d, raw);
+        const int l = (int)threadIdx.x;
+        bool in = true;
+        int d = l;
+        if (MU == 0) {
+            d = l + (n - s.cb);  // same x row
+        } else {
+            const int c = MU == 1 ? A.wcy : A.wcz, full = MU == 1 ? A.g.L[1] : A.g.L[2];
+            int q = (MU == 1 ? w.yy : w.zz) + (FWD ? 1 : -1);
+            if (c == full) q = q < 0 ? c - 1 : (q == c ? 0 : q);  // the chunk spans the dimension
+            else in = (unsigned)q < (unsigned)c;
+            d = l + (q - (MU == 1 ? w.yy : w.zz)) * (MU == 1 ? A.g.lxh : A.g.lxh * A.wcy);
+        }
+        if (in) W.get(w.buf, d, raw);
         else raw.load(R.in, 0, A.g.vh, n);
         hop_compute<float, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
     }
 }
 
-template <int SP, bool DAG, int EPI, bool IN2, bool SLOT>
+template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, bool NT>
 __global__ __launch_bounds__(WSPB, dslash_waves<SP>()) void k_dslash_walk(const DslashArgs A)
 {
     using RawT = typename RawSel<SP, float>::type;
@@ -807,8 +820,12 @@ __global__ __launch_bounds__(WSPB, dslash_waves<SP>()) void k_dslash_walk(const 
     }
     const Geom &g = A.g;
     const int vh = g.vh, lt = g.L[3], tw = A.twalk;
-    const int chunks = g.v3h / WSPB;
-    const int tb = sb / chunks, o = (sb - tb * chunks) * WSPB + (int)threadIdx.x;
+    const int ncy = g.L[1] / A.wcy, chunks = ncy * (g.L[2] / A.wcz);
+    const int tb = sb / chunks, c = sb - tb * chunks;
+    const int l = (int)threadIdx.x, xh = l % g.lxh, rz = l / g.lxh;
+    const int yy = rz % A.wcy, zz = rz / A.wcy;
+    // the thread's site within a timeslice
+    const int o = xh + g.sy * ((c % ncy) * A.wcy + yy) + g.sz * ((c / ncy) * A.wcz + zz);
     const int t0 = tb * tw;
     HopRes R;
     R.gauge = mkrsrc(A.gauge, A.gauge_span);
@@ -827,7 +844,7 @@ __global__ __launch_bounds__(WSPB, dslash_waves<SP>()) void k_dslash_walk(const 
         const int cb = t * g.st + o;
         RawT nxt;
         nxt.load(R.in, 0, vh, ((t + 1) % lt) * g.st + o);
-        const WalkPos w{t * g.st + (o - (int)threadIdx.x), k & 1};
+        const WalkPos w{k & 1, yy, zz};
         const Site s = site_of(g, cb, A.out_par);
         cpx<float> acc[12];
 #pragma unroll
@@ -845,7 +862,7 @@ __global__ __launch_bounds__(WSPB, dslash_waves<SP>()) void k_dslash_walk(const 
             default: walk_dir<SP, 3, false, DAG>(A, R, s, W, w, nxt, acc); break;
             }
         }
-        const double part = epilogue<SP, EPI, IN2, 0>(A, slot, cb, acc, kappa, a, alpha);
+        const double part = epilogue<SP, EPI, IN2, 0, NT>(A, slot, cb, acc, kappa, a, alpha);
         if constexpr (EPI != EPI_PLAIN) {
             // one wave = one 64-site reduction tile
             const double v = wave_sum(part);
@@ -895,6 +912,34 @@ inline int lanes_per_site(int nslot)
     return r;
 }
 
+// Chunk shape of the walk: cy rows x cz planes of full x rows with cy | Ly,
+// cz | Lz, a multiple of 64 sites up to WSPB, each 64 threads one aligned
+// 64-site tile (cy = Ly, or cy * Lx/2 a multiple of 64); the fewest halo
+// neighbours per site (2/cy + 2/cz, no term for a dimension the chunk spans),
+// then the largest chunk.  False if no shape fits.
+inline bool walk_chunk(const Geom &g, int &cy, int &cz)
+{
+    double best = 1e30;
+    int bs = 0;
+    for (int y = 1; y <= g.L[1]; y++) {
+        if (g.L[1] % y) continue;
+        for (int z = 1; z <= g.L[2]; z++) {
+            if (g.L[2] % z) continue;
+            const int cs = y * z * g.lxh;
+            if (cs > WSPB || cs % 64) continue;
+            if (y != g.L[1] && (y * g.lxh) % 64) continue;
+            const double halo = (y < g.L[1] ? 2.0 / y : 0.0) + (z < g.L[2] ? 2.0 / z : 0.0);
+            if (halo < best - 1e-12 || (halo < best + 1e-12 && cs > bs)) {
+                best = halo;
+                bs = cs;
+                cy = y;
+                cz = z;
+            }
+        }
+    }
+    return bs > 0;
+}
+
 // timeslices per block of the LDS walk (TM_LDS_TWALK; TM_LDS_WALK=0 disables the walk)
 inline int lds_twalk()
 {
@@ -910,21 +955,23 @@ static bool launch_walk(DslashArgs A, hipStream_t s)
     } else {
         int tw = lds_twalk();
         const uint64_t field = (uint64_t)A.g.vh * (SP == P32 ? 96 : 52);
-        if (tw < 1 || A.g.v3h % WSPB != 0 || field >= (1ull << 32)) return false;
+        if (tw < 1 || field >= (1ull << 32) || !walk_chunk(A.g, A.wcy, A.wcz)) return false;
         while (A.g.L[3] % tw) tw--;
         A.twalk = tw;
         A.in_span = (uint32_t)field;
         A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P32 ? 48 : 36), 0xFFFFFFFFull);
         static const int gouter = env_knob("TM_GROUP_OUTER", 0);
         A.gouter = gouter;
-        A.nblk_site = A.g.vh / WSPB / tw;
+        const int cs = A.wcy * A.wcz * A.g.lxh;
+        A.nblk_site = (A.g.v3h / cs) * (A.g.L[3] / tw);
         A.ntile = ntile_of(A.g);
         const int total = A.nblk_site * A.nslot;
         const int grid = A.swz ? 8 * ((total + 7) / 8) : total;
+        // outputs are streamed past L2 (non-temporal), keeping it for the halo lines
         if (A.st)
-            hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, true>), dim3(grid), dim3(WSPB), 0, s, A);
+            hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, true, true>), dim3(grid), dim3(cs), 0, s, A);
         else
-            hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, false>), dim3(grid), dim3(WSPB), 0, s, A);
+            hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, false, true>), dim3(grid), dim3(cs), 0, s, A);
         return true;
     }
 }

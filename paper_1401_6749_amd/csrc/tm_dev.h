@@ -137,6 +137,29 @@ struct Real<P64> {
 template <int P>
 struct SpinorIO;
 
+// 16- and 4-byte global stores; NT marks them non-temporal (streamed past
+// the caches), for outputs no kernel of the same pass reads again.
+typedef unsigned int tm_u32x4 __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ void st16(void *p, tm_u32x4 v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, (tm_u32x4 *)p);
+    else *(tm_u32x4 *)p = v;
+}
+template <bool NT>
+__device__ __forceinline__ void st4(void *p, uint32_t v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, (uint32_t *)p);
+    else *(uint32_t *)p = v;
+}
+template <bool NT, class V>
+__device__ __forceinline__ void st16v(void *p, const V &v)
+{
+    tm_u32x4 u;
+    __builtin_memcpy(&u, &v, 16);
+    st16<NT>(p, u);
+}
+
 template <>
 struct SpinorIO<P64> {
     static constexpr size_t bytes_per_site = 192;
@@ -150,12 +173,12 @@ struct SpinorIO<P64> {
             v[k] = cpx<T>{(T)q.x, (T)q.y};
         }
     }
-    template <class T>
+    template <class T, bool NT = false>
     __device__ static __forceinline__ void store(void *f, int vh, int i, const cpx<T> v[12])
     {
         double2 *p = (double2 *)f;
 #pragma unroll
-        for (int k = 0; k < 12; k++) p[(size_t)k * vh + i] = make_double2((double)v[k].re, (double)v[k].im);
+        for (int k = 0; k < 12; k++) st16v<NT>(&p[(size_t)k * vh + i], make_double2((double)v[k].re, (double)v[k].im));
     }
 };
 
@@ -173,14 +196,14 @@ struct SpinorIO<P32> {
             v[2 * g + 1] = cpx<T>{(T)q.z, (T)q.w};
         }
     }
-    template <class T>
+    template <class T, bool NT = false>
     __device__ static __forceinline__ void store(void *f, int vh, int i, const cpx<T> v[12])
     {
         float4 *p = (float4 *)f;
 #pragma unroll
         for (int g = 0; g < 6; g++)
-            p[(size_t)g * vh + i] = make_float4((float)v[2 * g].re, (float)v[2 * g].im, (float)v[2 * g + 1].re,
-                                                (float)v[2 * g + 1].im);
+            st16v<NT>(&p[(size_t)g * vh + i], make_float4((float)v[2 * g].re, (float)v[2 * g].im,
+                                                          (float)v[2 * g + 1].re, (float)v[2 * g + 1].im));
     }
 };
 
@@ -217,7 +240,7 @@ struct SpinorHalfIO {
             }
         }
     }
-    template <class T>
+    template <class T, bool NT = false>
     __device__ static __forceinline__ void store(void *f, int vh, int i, const cpx<T> v[12])
     {
         uint4 *p = (uint4 *)f;
@@ -234,9 +257,9 @@ struct SpinorHalfIO {
                 uint32_t hi = HalfCodec<P>::enc((float)v[4 * g + c].im * inv);
                 w[c] = lo | (hi << 16);
             }
-            p[(size_t)g * vh + i] = make_uint4(w[0], w[1], w[2], w[3]);
+            st16<NT>(&p[(size_t)g * vh + i], tm_u32x4{w[0], w[1], w[2], w[3]});
         }
-        ((float *)(p + 3 * (size_t)vh))[i] = mx;
+        st4<NT>(&((float *)(p + 3 * (size_t)vh))[i], __float_as_uint(mx));
     }
 };
 template <>

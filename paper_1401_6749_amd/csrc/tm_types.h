@@ -126,6 +126,7 @@ struct DslashArgs {
     uint32_t in_span, gauge_span;  // bytes reachable through the buffer resources (set by the launcher)
     int twalk;                     // timeslices walked per block (set by the launcher)
     int gouter;                    // slot groups slowest in the block order (set by the launcher)
+    int wcy, wcz;                  // timeslice-walk chunk: y rows x z planes of full x rows (set by the launcher)
     double *partial;            // [nslot][ntile]
     // EPI_CGUPD
     char *x, *r;
