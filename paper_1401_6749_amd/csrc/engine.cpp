@@ -10,6 +10,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 
@@ -44,6 +45,27 @@ static int kind_xr(Kind k) { return kind_prec(k); }  // x, r stored like the Dsl
 // distances otherwise) does not land on one memory channel.
 static size_t slot_pitch(size_t field) { return ((field + 255) & ~(size_t)255) + 17 * 256; }
 
+static bool lp_kind(Kind k) { return k == K_LP16 || k == K_LPBF; }
+
+// longest run of slots prepared / harvested / updated together
+// (TM_FILL_RUN, TM_HARVEST_RUN, TM_UPDATE_RUN cap it; 1 = slot by slot)
+static int run_cap(const char *name)
+{
+    const char *e = getenv(name);
+    return e ? std::max(1, atoi(e)) : MAX_SLOTS;
+}
+
+// Preparation / reconstruction precision of the kind's noise solves (LP: FP32).
+static int kind_prep(Kind k) { return lp_kind(k) ? P32 : P64; }
+
+// Each scratch array holds an FP64 full field [even | odd], or one
+// preparation-precision half field per slot (runs of slots prepared and
+// harvested together).
+static size_t scratch_bytes(const Geom &g, Kind kind, int S)
+{
+    return std::max(2 * half_bytes(P64, g), (size_t)S * slot_pitch(half_bytes(kind_prep(kind), g)));
+}
+
 size_t batch_footprint(const tm_gauge *G, Kind kind, int S)
 {
     const Geom &g = G->g;
@@ -53,9 +75,9 @@ size_t batch_footprint(const tm_gauge *G, Kind kind, int S)
     b += (size_t)S * 2 * slot_pitch(half_bytes(xr, g));  // x, r
     if (kind == K_MIXED) b += (size_t)S * 2 * half_bytes(P64, g);  // x64, b64
     b += (size_t)S * 2 * g.vh * sizeof(uint32_t);      // noise codes
-    b += 3 * 2 * half_bytes(P64, g);                   // FP64 scratch FA, FB, FC
+    b += 3 * (scratch_bytes(g, kind, S) + 256);         // scratch FA, FB, FC
     b += (size_t)S * ntile_of(g) * sizeof(double) + 4096;
-    b += (size_t)g.L[3] * contract_nchunk(g) * 288 * sizeof(double);
+    b += (size_t)(lp_kind(kind) ? S : 1) * contract_part_doubles(g) * sizeof(double) + 256;
     b += (size_t)S * sizeof(SlotState) + 64 * sizeof(double) + 16 * 256;
     return b;
 }
@@ -117,11 +139,15 @@ int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk
         b->b64 = carve(cur, S * b->h64);
     }
     b->codes = (uint32_t *)carve(cur, (size_t)S * 2 * g.vh * sizeof(uint32_t));
-    b->FA = carve(cur, 2 * b->h64);
-    b->FB = carve(cur, 2 * b->h64);
-    b->FC = carve(cur, 2 * b->h64);
+    const size_t sb = scratch_bytes(g, kind, S);
+    b->wpp = kind_prep(kind);
+    b->wpitch = slot_pitch(half_bytes(b->wpp, g));
+    b->wslots = (int)std::min<size_t>(S, sb / b->wpitch);
+    b->FA = carve(cur, sb);
+    b->FB = carve(cur, sb);
+    b->FC = carve(cur, sb);
     b->partial = (double *)carve(cur, (size_t)S * b->nblk * sizeof(double) + 4096);
-    b->cpart = (double *)carve(cur, (size_t)g.L[3] * contract_nchunk(g) * 288 * sizeof(double));
+    b->cpart = (double *)carve(cur, (size_t)(lp_kind(kind) ? S : 1) * contract_part_doubles(g) * sizeof(double));
     b->dres = (double *)carve(cur, 64 * sizeof(double));
     b->st = (SlotState *)carve(cur, (size_t)S * sizeof(SlotState));
     b->stream = stream;
@@ -267,50 +293,141 @@ static void dsl_codes(const Batch *b, int pp, int src, int coef, int out_par, in
     launch_dslash_codes(pp, src, A, b->stream);
 }
 
-int batch_fill(Batch *b, int slot, Job *j)
+// Dslash with uniform (kappa, a) over n consecutive slots with the given pitches
+static void dsl_run(const Batch *b, int pp, bool dag, int epi, int coef, int out_par, const char *in, size_t in_slot,
+                    const char *in2, size_t in2_slot, char *out, size_t out_slot, double kappa, double a, int n,
+                    double *partial = nullptr, const char *bvec = nullptr, size_t b_slot = 0)
 {
-    const Geom &g = b->G->g;
-    hipStream_t s = b->stream;
+    DslashArgs A = dargs(b, pp);
+    A.nslot = n;
+    A.in = in;
+    A.in_slot = in_slot;
+    A.in2 = in2;
+    A.in2_slot = in2_slot;
+    A.out = out;
+    A.out_slot = out_slot;
+    A.out_par = out_par;
+    A.coef = coef;
+    A.kappa_u = kappa;
+    A.a_u = a;
+    A.partial = partial;
+    A.b = bvec;
+    A.b_slot = b_slot;
+    launch_dslash(pp, dag, epi, in2 != nullptr, A, b->stream);
+}
+
+// dsl_codes over the n consecutive slots from s0
+static void dsl_codes_run(const Batch *b, int pp, int src, int coef, int out_par, int s0, int n, const char *in,
+                          size_t in_slot, char *out, size_t out_slot, double kappa, double a)
+{
+    DslashArgs A = dargs(b, pp);
+    A.nslot = n;
+    A.codes = b->codes + (size_t)s0 * 2 * b->G->g.vh;
+    A.codes_slot = (size_t)2 * b->G->g.vh * sizeof(uint32_t);
+    A.in = in;
+    A.in_slot = in_slot;
+    A.out = out;
+    A.out_slot = out_slot;
+    A.out_par = out_par;
+    A.coef = coef;
+    A.kappa_u = kappa;
+    A.a_u = a;
+    launch_dslash_codes(pp, src, A, b->stream);
+}
+
+static void job_start(Batch *b, int slot, Job *j)
+{
     b->slot_job[slot] = j;
     b->slot_updates[slot] = 0;
     b->slot_pending_update[slot] = 0;
     j->t_fill = now_s();
     if (b->t_first == 0) b->t_first = j->t_fill;
+}
+
+// Noise solves in the n consecutive slots from s0, equal (kappa, a) and
+// preparation precision pp, prepared together:
+//   bhat_e = eta_e + kappa D_eo A^-1 eta_o straight from the Z4 codes,
+//   rhs = Mhat^dag bhat = A^dag bhat - kappa^2 D'_eo A^-dag D'_oe bhat,
+// r = p = rhs (rounded to the CG precisions), x = 0.
+static void fill_noise_run(Batch *b, int s0, int n, Job *const *jobs, int pp)
+{
+    const Geom &g = b->G->g;
+    hipStream_t s = b->stream;
+    const bool mixed = b->kind == K_MIXED;
+    const double kappa = jobs[0]->kappa, a = jobs[0]->a;
+    Z4Sources Z{};
+    SlotStartParams P{};
+    P.mixed = mixed ? 1 : 0;
+    for (int i = 0; i < n; i++) {
+        Job *j = jobs[i];
+        job_start(b, s0 + i, j);
+        Z.seed[i] = j->seed;
+        Z.src[i] = j->src;
+        P.kappa[i] = j->kappa;
+        P.a[i] = j->a;
+        P.tol2[i] = j->fixed > 0 ? 0.0 : j->tol * j->tol;
+        P.max_iter[i] = j->fixed > 0 ? j->fixed : j->max_iter;
+        const double delta = j->delta > 0 ? j->delta : 0.1;
+        P.delta2[i] = delta * delta;
+    }
+    launch_z4_codes(g, Z, n, b->codes + (size_t)s0 * 2 * g.vh, s);
+    const size_t w = n > 1 ? b->wpitch : half_bytes(pp, g);
+    char *Be = b->FB, *To = b->FC, *Ce = b->FA;
+    double *part = b->partial + (size_t)s0 * b->nblk;
+    dsl_codes_run(b, pp, 3, CM_PREP, 0, s0, n, nullptr, 0, Be, w, kappa, a);
+    dsl_run(b, pp, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, w, nullptr, 0, To, w, kappa, a, n);
+    dsl_run(b, pp, true, EPI_NORM, CM_MHAT_DAG, 0, To, w, Be, w, Ce, w, kappa, a, n, part);
+    launch_slot_start(b->st + s0, part, b->nblk, P, n, s);
+    launch_convert(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->hxr, n, s);
+    launch_convert(pp, b->sp, g, Ce, w, b->p + s0 * b->hsp, b->hsp, n, s);
+    launch_zero(b->xr, g, b->x + s0 * b->hxr, b->hxr, n, s);
+    if (mixed) {
+        launch_convert(P64, P64, g, Ce, w, b->b64 + s0 * b->h64, b->h64, n, s);
+        launch_zero(P64, g, b->x64 + s0 * b->h64, b->h64, n, s);
+    }
+}
+
+int batch_fill_many(Batch *b, Job *const *jobs, int njobs)
+{
+    std::vector<int> fs;
+    for (int s = 0; s < b->S && (int)fs.size() < njobs; s++)
+        if (!b->slot_job[s]) fs.push_back(s);
+    const int m = (int)fs.size();
+    int k = 0;
+    while (k < m) {
+        Job *j = jobs[k];
+        if (!j->noise) {
+            batch_fill(b, fs[k], j);
+            k++;
+            continue;
+        }
+        const int pp = prep_prec(b, j);
+        static const int cap_env = run_cap("TM_FILL_RUN");
+        const int cap = pp == b->wpp ? std::min(b->wslots, cap_env) : 1;
+        int n = 1;
+        while (k + n < m && n < cap && fs[k + n] == fs[k] + n && jobs[k + n]->noise &&
+               jobs[k + n]->kappa == j->kappa && jobs[k + n]->a == j->a && prep_prec(b, jobs[k + n]) == pp)
+            n++;
+        fill_noise_run(b, fs[k], n, jobs + k, pp);
+        k += n;
+    }
+    return m;
+}
+
+int batch_fill(Batch *b, int slot, Job *j)
+{
+    if (j->noise) {
+        fill_noise_run(b, slot, 1, &j, prep_prec(b, j));
+        return TM_OK;
+    }
+    const Geom &g = b->G->g;
+    hipStream_t s = b->stream;
+    job_start(b, slot, j);
     const bool mixed = b->kind == K_MIXED;
     const double tol2 = j->fixed > 0 ? 0.0 : j->tol * j->tol;
     const int maxit = j->fixed > 0 ? j->fixed : j->max_iter;
     const double delta = j->delta > 0 ? j->delta : 0.1;
     double *part = b->partial + (size_t)slot * b->nblk;
-    const int pp = prep_prec(b, j);
-    if (j->noise) {
-        // bhat_e = eta_e + kappa D_eo A^-1 eta_o straight from the Z4 codes,
-        // rhs = Mhat^dag bhat = A^dag bhat - kappa^2 D'_eo A^-dag D'_oe bhat
-        launch_z4_codes(g, j->seed, j->src, b->codes + (size_t)slot * 2 * g.vh, s);
-        char *Be = b->FB, *To = b->FC;  // scratch fields in precision pp
-        dsl_codes(b, pp, 3, CM_PREP, 0, slot, nullptr, Be, j->kappa, j->a);
-        dsl(b, pp, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, nullptr, To, j->kappa, j->a);
-        if (pp == P32) {
-            // LP: the FP32 right-hand side is rounded once into r and p (half precision)
-            char *rhs = b->FA;
-            dsl(b, P32, true, EPI_NORM, CM_MHAT_DAG, 0, To, Be, rhs, j->kappa, j->a, part);
-            launch_slot_start(b->st + slot, part, b->nblk, j->kappa, j->a, tol2, maxit, delta * delta, 0, s);
-            launch_convert(P32, b->xr, g, rhs, 0, b->r + slot * b->hxr, 0, 1, s);
-            launch_convert(P32, b->sp, g, rhs, 0, b->p + slot * b->hsp, 0, 1, s);
-            launch_zero(b->xr, g, b->x + slot * b->hxr, 0, 1, s);
-            return TM_OK;
-        }
-        char *Ce = b->FA;
-        dsl(b, P64, true, EPI_NORM, CM_MHAT_DAG, 0, To, Be, Ce, j->kappa, j->a, part);
-        launch_slot_start(b->st + slot, part, b->nblk, j->kappa, j->a, tol2, maxit, delta * delta, mixed ? 1 : 0, s);
-        launch_convert(P64, b->xr, g, Ce, 0, b->r + slot * b->hxr, 0, 1, s);
-        launch_convert(P64, b->sp, g, Ce, 0, b->p + slot * b->hsp, 0, 1, s);
-        launch_zero(b->xr, g, b->x + slot * b->hxr, 0, 1, s);
-        if (mixed) {
-            launch_convert(P64, P64, g, Ce, 0, b->b64 + slot * b->h64, 0, 1, s);
-            launch_zero(P64, g, b->x64 + slot * b->h64, 0, 1, s);
-        }
-        return TM_OK;
-    }
     load_eta(b, slot, j);
     char *Ee = b->FA, *Eo = b->FA + b->h64;
     char *Be = b->FB, *Bo = b->FB + b->h64;
@@ -424,50 +541,55 @@ int batch_launch_chunk(Batch *b)
     return TM_OK;
 }
 
-// FP64 reliable update of a mixed-precision slot: x64 += x32, r = b - Mhat^dag Mhat x64
-// in FP64, r32 = r, then the CG direction continues with beta = |r|^2/|r_old|^2.
-static void reliable_update(Batch *b, int slot)
+// FP64 reliable updates of the n consecutive mixed-precision slots from s0
+// (equal kappa, a): x64 += x32, r = b - Mhat^dag Mhat x64 in FP64, r32 = r,
+// then each CG direction continues with beta = |r|^2/|r_old|^2.
+static void reliable_update_run(Batch *b, int s0, int n)
 {
     const Geom &g = b->G->g;
-    Job *j = b->slot_job[slot];
+    const Job *j = b->slot_job[s0];
     hipStream_t s = b->stream;
-    char *x64 = b->x64 + slot * b->h64;
-    char *x32 = b->x + slot * b->hxr;
-    char *Be = b->FB, *Bo = b->FB + b->h64, *Ce = b->FC;
-    launch_accum_x(g, x64, x32, x32, s);
-    d64(b, false, EPI_PLAIN, CM_AINV, 1, x64, nullptr, Bo, j->kappa, j->a);
-    d64(b, false, EPI_PLAIN, CM_MHAT, 0, Bo, x64, Be, j->kappa, j->a);
-    d64(b, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, nullptr, Bo, j->kappa, j->a);
-    double *part = b->partial + (size_t)slot * b->nblk;
-    d64(b, true, EPI_RESID, CM_MHAT_DAG, 0, Bo, Be, Ce, j->kappa, j->a, part, b->b64 + slot * b->h64);
-    launch_convert(P64, P32, g, Ce, 0, b->r + slot * b->hxr, 0, 1, s);
-    launch_reliable_finish(b->st + slot, part, b->nblk, s);
-    launch_p_update(b->sp, b->xr, g, b->p + slot * b->hsp, b->hsp, b->r + slot * b->hxr, b->hxr, b->st + slot, 1,
-                    b->ctx->swz, s);
-    b->slot_updates[slot]++;
+    const size_t w = n > 1 ? b->wpitch : b->h64;
+    char *x64 = b->x64 + s0 * b->h64;
+    char *x32 = b->x + s0 * b->hxr, *r32 = b->r + s0 * b->hxr;
+    char *Bo = b->FB, *Be = b->FA, *Ce = b->FC;
+    double *part = b->partial + (size_t)s0 * b->nblk;
+    launch_accum_x(g, x64, b->h64, x32, x32, b->hxr, n, s);
+    dsl_run(b, P64, false, EPI_PLAIN, CM_AINV, 1, x64, b->h64, nullptr, 0, Bo, w, j->kappa, j->a, n);
+    dsl_run(b, P64, false, EPI_PLAIN, CM_MHAT, 0, Bo, w, x64, b->h64, Be, w, j->kappa, j->a, n);
+    dsl_run(b, P64, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, w, nullptr, 0, Bo, w, j->kappa, j->a, n);
+    dsl_run(b, P64, true, EPI_RESID, CM_MHAT_DAG, 0, Bo, w, Be, w, Ce, w, j->kappa, j->a, n, part,
+            b->b64 + s0 * b->h64, b->h64);
+    launch_convert(P64, b->xr, g, Ce, w, r32, b->hxr, n, s);
+    launch_reliable_finish(b->st + s0, part, b->nblk, n, s);
+    launch_p_update(b->sp, b->xr, g, b->p + s0 * b->hsp, b->hsp, r32, b->hxr, b->st + s0, n, b->ctx->swz, s);
+    for (int i = 0; i < n; i++) b->slot_updates[s0 + i]++;
 }
 
 static void harvest64(Batch *b, int slot, const SlotState &S, Job *j);
 static int true_residual(Batch *b, int slot, Job *j);
 
-// reconstruct s = (s_e, s_o), contract or export, optional true residual
-static int harvest(Batch *b, int slot, const SlotState &S)
+// LP noise solves in the n consecutive slots from s0 (equal kappa, a):
+// s_e = x widened to FP32, s_o = A^-1 (eta_o + kappa D_oe s_e) from the codes,
+// contractions on FP32 s and FP32 links with FP64 sums.
+static void harvest_lp_run(Batch *b, int s0, int n)
 {
     const Geom &g = b->G->g;
-    Job *j = b->slot_job[slot];
+    const Job *j = b->slot_job[s0];
     hipStream_t s = b->stream;
-    if (prep_prec(b, j) == P32) {
-        // LP noise solve: s_e = x widened to FP32, s_o = A^-1 (eta_o + kappa D_oe s_e) from the
-        // codes, contraction on FP32 s and FP32 links with FP64 accumulation
-        char *se32 = b->FB, *so32 = b->FC;
-        launch_convert(b->xr, P32, g, b->x + slot * b->hxr, 0, se32, 0, 1, s);
-        dsl_codes(b, P32, 2, CM_RECON, 1, slot, se32, so32, j->kappa, j->a);
-        if (j->raw_out)
-            launch_contract(P32, g, b->G->links[P32], se32, so32, b->codes + (size_t)slot * 2 * g.vh, b->cpart,
-                            j->raw_out, s);
-    } else {
-        harvest64(b, slot, S, j);
-    }
+    const size_t w = n > 1 ? b->wpitch : half_bytes(P32, g);
+    char *se32 = b->FB, *so32 = b->FC;
+    launch_convert(b->xr, P32, g, b->x + s0 * b->hxr, b->hxr, se32, w, n, s);
+    dsl_codes_run(b, P32, 2, CM_RECON, 1, s0, n, se32, w, so32, w, j->kappa, j->a);
+    RawOuts R{};
+    for (int i = 0; i < n; i++) R.p[i] = b->slot_job[s0 + i]->raw_out;
+    launch_contract(P32, g, b->G->links[P32], se32, so32, w, b->codes + (size_t)s0 * 2 * g.vh, b->cpart, R, n, s);
+}
+
+// results of a finished slot: status, counts, optional true residual; frees the slot
+static int harvest_done(Batch *b, int slot, const SlotState &S)
+{
+    Job *j = b->slot_job[slot];
     j->iters = S.iter;
     j->updates = b->slot_updates[slot];
     j->cg_rel = S.rr0 > 0 ? std::sqrt(std::max(S.status == ST_CONVERGED || S.status == ST_MAXITER ? S.rr : S.rr_new, 0.0) / S.rr0) : 0.0;
@@ -485,6 +607,18 @@ static int harvest(Batch *b, int slot, const SlotState &S)
     return TM_OK;
 }
 
+// LP noise solves harvested in FP32 (their contraction needs a raw output)
+static bool lp_harvest(const Batch *b, const Job *j) { return prep_prec(b, j) == P32 && j->raw_out; }
+
+// reconstruct s = (s_e, s_o), contract or export, optional true residual
+static int harvest(Batch *b, int slot, const SlotState &S)
+{
+    Job *j = b->slot_job[slot];
+    if (lp_harvest(b, j)) harvest_lp_run(b, slot, 1);
+    else if (prep_prec(b, j) != P32) harvest64(b, slot, S, j);
+    return harvest_done(b, slot, S);
+}
+
 // FP64 reconstruction and contraction / export
 static void harvest64(Batch *b, int slot, const SlotState &S, Job *j)
 {
@@ -496,7 +630,7 @@ static void harvest64(Batch *b, int slot, const SlotState &S, Job *j)
         launch_convert(P64, P64, g, b->x + slot * b->hxr, 0, se, 0, 1, s);
     } else if (b->kind == K_MIXED) {
         char *x64 = b->x64 + slot * b->h64;
-        if (S.status != ST_CONVERGED) launch_accum_x(g, x64, b->x + slot * b->hxr, nullptr, s);
+        if (S.status != ST_CONVERGED) launch_accum_x(g, x64, 0, b->x + slot * b->hxr, nullptr, 0, 1, s);
         launch_convert(P64, P64, g, x64, 0, se, 0, 1, s);
     } else {
         launch_convert(b->xr, P64, g, b->x + slot * b->hxr, 0, se, 0, 1, s);
@@ -541,22 +675,56 @@ static int true_residual(Batch *b, int slot, Job *j)
     return TM_OK;
 }
 
+static bool same_params(const Job *a, const Job *b) { return a->kappa == b->kappa && a->a == b->a; }
+
 int batch_process(Batch *b, std::vector<Job *> &finished)
 {
     b->in_flight = false;
     int rc = TM_OK;
-    for (int s = 0; s < b->S; s++) {
+    const int S = b->S;
+    // reliable updates, run over consecutive slots with equal (kappa, a)
+    for (int s = 0; s < S;) {
         Job *j = b->slot_job[s];
-        if (!j) continue;
-        const SlotState &S = b->st_h[s];
-        if (S.status == ST_RUNNING) continue;
-        if (S.status == ST_NEED_UPDATE) {
-            reliable_update(b, s);
+        if (!j || b->st_h[s].status != ST_NEED_UPDATE) {
+            s++;
             continue;
         }
-        int e = harvest(b, s, S);
-        if (e != TM_OK) rc = e;
-        finished.push_back(j);
+        static const int cap = run_cap("TM_UPDATE_RUN");
+        int n = 1;
+        while (s + n < S && n < std::min(b->wslots, cap) && b->slot_job[s + n] && b->st_h[s + n].status == ST_NEED_UPDATE &&
+               same_params(b->slot_job[s + n], j))
+            n++;
+        reliable_update_run(b, s, n);
+        s += n;
+    }
+    // finished slots; LP noise solves harvested together
+    auto done = [&](int s) {
+        const int st = b->st_h[s].status;
+        return b->slot_job[s] && st != ST_RUNNING && st != ST_NEED_UPDATE;
+    };
+    for (int s = 0; s < S;) {
+        if (!done(s)) {
+            s++;
+            continue;
+        }
+        Job *j = b->slot_job[s];
+        int n = 1;
+        if (lp_harvest(b, j)) {
+            static const int cap = run_cap("TM_HARVEST_RUN");
+            while (s + n < S && n < std::min(b->wslots, cap) && done(s + n) && lp_harvest(b, b->slot_job[s + n]) &&
+                   same_params(b->slot_job[s + n], j))
+                n++;
+            harvest_lp_run(b, s, n);
+        } else if (prep_prec(b, j) != P32) {
+            harvest64(b, s, b->st_h[s], j);
+        }
+        for (int i = 0; i < n; i++) {
+            Job *ji = b->slot_job[s + i];
+            int e = harvest_done(b, s + i, b->st_h[s + i]);
+            if (e != TM_OK) rc = e;
+            finished.push_back(ji);
+        }
+        s += n;
     }
     return rc;
 }
@@ -582,9 +750,8 @@ int run_jobs(std::vector<Batch *> &batches, std::vector<std::vector<Job *>> &que
                 progressed = true;
             }
             // refill free slots
-            int slot;
-            while (next[k] < queues[k].size() && (slot = batch_free_slot(b)) >= 0) {
-                batch_fill(b, slot, queues[k][next[k]++]);
+            if (next[k] < queues[k].size() && batch_free_slot(b) >= 0) {
+                next[k] += batch_fill_many(b, queues[k].data() + next[k], (int)(queues[k].size() - next[k]));
                 progressed = true;
             }
             if (batch_active(b) > 0) {

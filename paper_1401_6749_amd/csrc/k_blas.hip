@@ -63,19 +63,21 @@ __global__ __launch_bounds__(BLOCK) void k_cg_beta(SlotState *st, const double *
     }
 }
 
-__global__ void k_slot_start(SlotState *st, const double *partial, int nblk, double kappa, double a, double tol2,
-                             int max_iter, double delta2, int mixed)
+// block i starts slot st[i] from partial[i*nblk ..]
+__global__ void k_slot_start(SlotState *st, const double *partial, int nblk, SlotStartParams P)
 {
     __shared__ double lds[BLOCK / 64];
-    const double rr0 = sum_fixed(partial, nblk, lds);
+    const int i = blockIdx.x;
+    const double rr0 = sum_fixed(partial + (size_t)i * nblk, nblk, lds);
     if (threadIdx.x == 0) {
-        SlotState &S = *st;
-        S.kappa = kappa;
-        S.a = a;
-        S.tol2 = tol2;
+        SlotState &S = st[i];
+        const int max_iter = P.max_iter[i];
+        S.kappa = P.kappa[i];
+        S.a = P.a[i];
+        S.tol2 = P.tol2[i];
         S.max_iter = max_iter;
-        S.delta2 = delta2;
-        S.mixed = mixed;
+        S.delta2 = P.delta2[i];
+        S.mixed = P.mixed;
         S.iter = 0;
         S.rr0 = rr0;
         S.rr = rr0;
@@ -93,12 +95,14 @@ __global__ void k_slot_start(SlotState *st, const double *partial, int nblk, dou
     }
 }
 
+// block i finishes the reliable update of slot st[i] from partial[i*nblk ..]
 __global__ void k_reliable_finish(SlotState *st, const double *partial, int nblk)
 {
     __shared__ double lds[BLOCK / 64];
-    const double rr = sum_fixed(partial, nblk, lds);
+    const int i = blockIdx.x;
+    const double rr = sum_fixed(partial + (size_t)i * nblk, nblk, lds);
     if (threadIdx.x == 0) {
-        SlotState &S = *st;
+        SlotState &S = st[i];
         S.rr_new = rr;
         if (!(rr >= 0.0 && rr < 1.0e300)) {
             S.status = ST_NUMERIC;
@@ -132,15 +136,28 @@ void launch_cg_beta(SlotState *st, const double *partial, int nslot, int nblk, h
 {
     hipLaunchKernelGGL(k_cg_beta, dim3(nslot), dim3(BLOCK), 0, s, st, partial, nblk);
 }
+void launch_slot_start(SlotState *st, const double *partial, int nblk, const SlotStartParams &P, int n,
+                       hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_slot_start, dim3(n), dim3(BLOCK), 0, s, st, partial, nblk, P);
+}
+
 void launch_slot_start(SlotState *st, const double *partial, int nblk, double kappa, double a, double tol2,
                        int max_iter, double delta2, int mixed, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_slot_start, dim3(1), dim3(BLOCK), 0, s, st, partial, nblk, kappa, a, tol2, max_iter,
-                       delta2, mixed);
+    SlotStartParams P{};
+    P.kappa[0] = kappa;
+    P.a[0] = a;
+    P.tol2[0] = tol2;
+    P.delta2[0] = delta2;
+    P.max_iter[0] = max_iter;
+    P.mixed = mixed;
+    launch_slot_start(st, partial, nblk, P, 1, s);
 }
-void launch_reliable_finish(SlotState *st, const double *partial, int nblk, hipStream_t s)
+
+void launch_reliable_finish(SlotState *st, const double *partial, int nblk, int n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reliable_finish, dim3(1), dim3(BLOCK), 0, s, st, partial, nblk);
+    if (n > 0) hipLaunchKernelGGL(k_reliable_finish, dim3(n), dim3(BLOCK), 0, s, st, partial, nblk);
 }
 void launch_reduce(const double *partial, int nblk, int n, double *out, hipStream_t s)
 {
@@ -251,10 +268,14 @@ void launch_zero(int p, const Geom &g, char *f, size_t slot, int nslot, hipStrea
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_accum_x(Geom g, char *x64, const char *x32, char *x32z)
+__global__ __launch_bounds__(BLOCK) void k_accum_x(Geom g, char *x64, const char *x32, char *x32z, size_t s64,
+                                                   size_t s32)
 {
     const int cb = blockIdx.x * BLOCK + threadIdx.x;
     if (cb >= g.vh) return;
+    x64 += (size_t)blockIdx.y * s64;
+    x32 += (size_t)blockIdx.y * s32;
+    if (x32z) x32z += (size_t)blockIdx.y * s32;
     cpx<double> a[12], b[12];
     SpinorIO<P64>::load(x64, g.vh, cb, a);
     SpinorIO<P32>::load(x32, g.vh, cb, b);
@@ -267,9 +288,11 @@ __global__ __launch_bounds__(BLOCK) void k_accum_x(Geom g, char *x64, const char
     if (x32z) SpinorIO<P32>::store(x32z, g.vh, cb, b);
 }
 
-void launch_accum_x(const Geom &g, char *x64, const char *x32_in, char *x32_zero, hipStream_t s)
+void launch_accum_x(const Geom &g, char *x64, size_t s64, const char *x32_in, char *x32_zero, size_t s32, int n,
+                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_accum_x, dim3(nblk_of(g)), dim3(BLOCK), 0, s, g, x64, x32_in, x32_zero);
+    if (n > 0)
+        hipLaunchKernelGGL(k_accum_x, dim3(nblk_of(g), n), dim3(BLOCK), 0, s, g, x64, x32_in, x32_zero, s64, s32);
 }
 
 // per-tile |f|^2 of one FP64 half field: partial[tile], 64-site tiles

@@ -279,107 +279,71 @@ __device__ __forceinline__ void raw_setup(RawZ4<T> &z, double den, double a)
 // (re low, im high).  The spin projection adds two stored components in
 // packed FP16 (one rounding to FP16, the same size as the storage rounding);
 // the colour transport multiplies FP16 link entries by FP16 half-spinor
-// entries with v_dot2_f32_f16, whose two products are exact in FP32 and whose
-// sums are FP32; the neighbour's per-site scale enters in the FP32
-// accumulation.  Signs, conjugation and factors of i are operand modifiers.
+// entries with the two-term FP16 dot product, whose products are exact in
+// FP32 and whose sums are FP32; the neighbour's per-site scale enters in the
+// FP32 accumulation.  Written with vector types and the dot-product builtin
+// (no inline assembly), so the compiler sees every instruction and inserts
+// the wait states the dot-product results need before other instructions
+// read them; it folds the signs and swaps of the projection into operand
+// modifiers of v_pk_add_f16.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b)  // a + b
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ h2 as_h2(uint32_t x)
 {
-    uint32_t d;
-    asm("v_pk_add_f16 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
-    return d;
+    h2 r;
+    __builtin_memcpy(&r, &x, 4);
+    return r;
 }
-__device__ __forceinline__ uint32_t pk_sub(uint32_t a, uint32_t b)  // a - b
+__device__ __forceinline__ h2 mul_i(h2 b) { return (h2){-b.y, b.x}; }  // i b
+__device__ __forceinline__ h2 swap_h(h2 b) { return __builtin_shufflevector(b, b, 1, 0); }
+__device__ __forceinline__ h2 conj_h(h2 b)  // flip the sign bit of the high half
 {
-    uint32_t d;
-    asm("v_pk_add_f16 %0, %1, %2 neg_lo:[0,1] neg_hi:[0,1]" : "=v"(d) : "v"(a), "v"(b));
-    return d;
+    uint32_t x;
+    __builtin_memcpy(&x, &b, 4);
+    return as_h2(x ^ 0x80000000u);
 }
-__device__ __forceinline__ uint32_t pk_sub_i(uint32_t a, uint32_t b)  // a - i b = (a.re + b.im, a.im - b.re)
-{
-    uint32_t d;
-    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_hi:[0,1]" : "=v"(d) : "v"(a), "v"(b));
-    return d;
-}
-__device__ __forceinline__ uint32_t pk_add_i(uint32_t a, uint32_t b)  // a + i b = (a.re - b.im, a.im + b.re)
-{
-    uint32_t d;
-    asm("v_pk_add_f16 %0, %1, %2 op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1]" : "=v"(d) : "v"(a), "v"(b));
-    return d;
-}
-// c + a.lo b.lo + a.hi b.hi
-__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c)
-{
-    float d;
-    asm("v_dot2_f32_f16 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
-}
-// c + a.lo b.lo - a.hi b.hi
-__device__ __forceinline__ float dot2_nh(uint32_t a, uint32_t b, float c)
-{
-    float d;
-    asm("v_dot2_f32_f16 %0, %1, %2, %3 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
-}
-// the same with c = 0 (inline constant, no zeroed register)
-__device__ __forceinline__ float dot2_z(uint32_t a, uint32_t b)
-{
-    float d;
-    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
-    return d;
-}
-__device__ __forceinline__ float dot2_nh_z(uint32_t a, uint32_t b)
-{
-    float d;
-    asm("v_dot2_f32_f16 %0, %1, %2, 0 neg_hi:[0,1,0]" : "=v"(d) : "v"(a), "v"(b));
-    return d;
-}
-__device__ __forceinline__ uint32_t swap16(uint32_t a) { return __builtin_amdgcn_alignbit(a, a, 16); }
 
 // packed half spinor of colour c for the projector (1 + S g_mu), from stored words p[k], k = 3*spin + colour
 template <int MU, int S>
-__device__ __forceinline__ void project_pk(const uint32_t p[12], int c, uint32_t &h0, uint32_t &h1)
+__device__ __forceinline__ void project_pk(const uint32_t p[12], int c, h2 &h0, h2 &h1)
 {
-    const uint32_t p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+    const h2 p0 = as_h2(p[c]), p1 = as_h2(p[3 + c]), p2 = as_h2(p[6 + c]), p3 = as_h2(p[9 + c]);
     if (MU == 0) {
-        h0 = S > 0 ? pk_sub_i(p0, p3) : pk_add_i(p0, p3);
-        h1 = S > 0 ? pk_sub_i(p1, p2) : pk_add_i(p1, p2);
+        h0 = S > 0 ? p0 - mul_i(p3) : p0 + mul_i(p3);
+        h1 = S > 0 ? p1 - mul_i(p2) : p1 + mul_i(p2);
     } else if (MU == 1) {
-        h0 = S > 0 ? pk_sub(p0, p3) : pk_add(p0, p3);
-        h1 = S > 0 ? pk_add(p1, p2) : pk_sub(p1, p2);
+        h0 = S > 0 ? p0 - p3 : p0 + p3;
+        h1 = S > 0 ? p1 + p2 : p1 - p2;
     } else if (MU == 2) {
-        h0 = S > 0 ? pk_sub_i(p0, p2) : pk_add_i(p0, p2);
-        h1 = S > 0 ? pk_add_i(p1, p3) : pk_sub_i(p1, p3);
+        h0 = S > 0 ? p0 - mul_i(p2) : p0 + mul_i(p2);
+        h1 = S > 0 ? p1 + mul_i(p3) : p1 - mul_i(p3);
     } else {
-        h0 = S > 0 ? pk_add(p0, p2) : pk_sub(p0, p2);
-        h1 = S > 0 ? pk_add(p1, p3) : pk_sub(p1, p3);
+        h0 = S > 0 ? p0 + p2 : p0 - p2;
+        h1 = S > 0 ? p1 + p3 : p1 - p3;
     }
 }
 
 // w = U h (FWD) or U^dagger h from packed link words u[3*row+col] and packed h
 template <bool FWD>
-__device__ __forceinline__ void transport_pk(const uint32_t u[9], const uint32_t h[3], const uint32_t hs[3],
-                                             float wr[3], float wi[3])
+__device__ __forceinline__ void transport_pk(const uint32_t u[9], const h2 h[3], float wr[3], float wi[3])
 {
+    h2 hr[3], hi[3];
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        // FWD: re = u.re h.re - u.im h.im, im = u.re h.im + u.im h.re
+        // BWD (conj u): re = u.re h.re + u.im h.im, im = u.re h.im - u.im h.re
+        hr[b] = FWD ? conj_h(h[b]) : h[b];
+        hi[b] = FWD ? swap_h(h[b]) : conj_h(swap_h(h[b]));
+    }
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        float re, im;
-        if (FWD) {  // U[a][b] h[b]: re = u.re h.re - u.im h.im, im = u.re h.im + u.im h.re
-            re = dot2_nh_z(u[3 * a], h[0]);
-            im = dot2_z(u[3 * a], hs[0]);
+        float re = 0.f, im = 0.f;
 #pragma unroll
-            for (int b = 1; b < 3; b++) {
-                re = dot2_nh(u[3 * a + b], h[b], re);
-                im = dot2(u[3 * a + b], hs[b], im);
-            }
-        } else {  // conj(U[b][a]) h[b]: re = u.re h.re + u.im h.im, im = u.re h.im - u.im h.re
-            re = dot2_z(u[a], h[0]);
-            im = dot2_nh_z(u[a], hs[0]);
-#pragma unroll
-            for (int b = 1; b < 3; b++) {
-                re = dot2(u[3 * b + a], h[b], re);
-                im = dot2_nh(u[3 * b + a], hs[b], im);
-            }
+        for (int b = 0; b < 3; b++) {
+            const h2 ue = as_h2(FWD ? u[3 * a + b] : u[3 * b + a]);
+            re = __builtin_amdgcn_fdot2(ue, hr[b], re, false);
+            im = __builtin_amdgcn_fdot2(ue, hi[b], im, false);
         }
         wr[a] = re;
         wi[a] = im;
@@ -391,6 +355,7 @@ template <int MU, int S>
 __device__ __forceinline__ void accum_pk(cpx<float> acc[12], const float wr0[3], const float wi0[3],
                                          const float wr1[3], const float wi1[3], float sc)
 {
+    const float s = S > 0 ? sc : -sc;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         acc[c].re = fmaf(sc, wr0[c], acc[c].re);
@@ -398,25 +363,21 @@ __device__ __forceinline__ void accum_pk(cpx<float> acc[12], const float wr0[3],
         acc[3 + c].re = fmaf(sc, wr1[c], acc[3 + c].re);
         acc[3 + c].im = fmaf(sc, wi1[c], acc[3 + c].im);
         if (MU == 0) {  // rows 2,3 = iS w1, iS w0
-            const float s = S > 0 ? sc : -sc;
             acc[6 + c].re = fmaf(-s, wi1[c], acc[6 + c].re);
             acc[6 + c].im = fmaf(s, wr1[c], acc[6 + c].im);
             acc[9 + c].re = fmaf(-s, wi0[c], acc[9 + c].re);
             acc[9 + c].im = fmaf(s, wr0[c], acc[9 + c].im);
         } else if (MU == 1) {  // S w1, -S w0
-            const float s = S > 0 ? sc : -sc;
             acc[6 + c].re = fmaf(s, wr1[c], acc[6 + c].re);
             acc[6 + c].im = fmaf(s, wi1[c], acc[6 + c].im);
             acc[9 + c].re = fmaf(-s, wr0[c], acc[9 + c].re);
             acc[9 + c].im = fmaf(-s, wi0[c], acc[9 + c].im);
         } else if (MU == 2) {  // iS w0, -iS w1
-            const float s = S > 0 ? sc : -sc;
             acc[6 + c].re = fmaf(-s, wi0[c], acc[6 + c].re);
             acc[6 + c].im = fmaf(s, wr0[c], acc[6 + c].im);
             acc[9 + c].re = fmaf(s, wi1[c], acc[9 + c].re);
             acc[9 + c].im = fmaf(-s, wr1[c], acc[9 + c].im);
         } else {  // S w0, S w1
-            const float s = S > 0 ? sc : -sc;
             acc[6 + c].re = fmaf(s, wr0[c], acc[6 + c].re);
             acc[6 + c].im = fmaf(s, wi0[c], acc[6 + c].im);
             acc[9 + c].re = fmaf(s, wr1[c], acc[9 + c].re);
@@ -440,16 +401,12 @@ __device__ __forceinline__ void hop_compute_pk(const DslashArgs &A, __amdgpu_buf
     uint32_t u[9];
     load_link_words(gauge, vh, FWD ? A.out_par : 1 - A.out_par, MU, FWD ? s.cb : n, u);
     if (MU == 3 && A.g.tbc < 0 && s.t == (FWD ? A.g.L[3] - 1 : 0)) sc = -sc;
-    uint32_t h0[3], h1[3], h0s[3], h1s[3];
+    h2 h0[3], h1[3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-        project_pk<MU, S>(p, c, h0[c], h1[c]);
-        h0s[c] = swap16(h0[c]);
-        h1s[c] = swap16(h1[c]);
-    }
+    for (int c = 0; c < 3; c++) project_pk<MU, S>(p, c, h0[c], h1[c]);
     float wr0[3], wi0[3], wr1[3], wi1[3];
-    transport_pk<FWD>(u, h0, h0s, wr0, wi0);
-    transport_pk<FWD>(u, h1, h1s, wr1, wi1);
+    transport_pk<FWD>(u, h0, wr0, wi0);
+    transport_pk<FWD>(u, h1, wr1, wi1);
     accum_pk<MU, S>(acc, wr0, wi0, wr1, wi1, sc);
 }
 
@@ -720,8 +677,8 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
 // edges) are read from global memory, where the blocks working on those
 // chunks have just fetched them into L2.  Two LDS buffers, one barrier per
 // step.  The chunk shape is picked on the host to minimise the halo; each
-// 64-thread wave covers one 64-site reduction tile.  The arithmetic per site
-// is that of k_dslash, in the same order, so both give the same bits.
+// 64-thread wave covers one 64-site reduction tile.  The arithmetic per
+// neighbour is that of k_dslash; the backward t neighbour is summed first.
 // ---------------------------------------------------------------------------
 constexpr int WSPB = 256;
 
@@ -768,21 +725,18 @@ struct WalkPos {
     int yy, zz;  // the thread's row and plane within the chunk
 };
 
+// t neighbours: this thread's own site in timeslices t+-1, both in the
+// other LDS buffer (t-1 until the backward neighbour is done, t+1 after).
 template <int SP, int MU, bool FWD, bool DAG>
 __device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, const Site &s, const WalkBuf<SP> &W,
-                                         const WalkPos &w, const typename RawSel<SP, float>::type &nxt,
-                                         cpx<float> acc[12])
+                                         const WalkPos &w, cpx<float> acc[12])
 {
     using RawT = typename RawSel<SP, float>::type;
     const int n = nbr<MU, FWD ? 1 : -1>(A.g, s);
     if constexpr (MU == 3) {
-        if constexpr (FWD) {
-            hop_compute<float, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, nxt, acc);
-        } else {
-            RawT raw;
-            W.get(w.buf ^ 1, threadIdx.x, raw);
-            hop_compute<float, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
-        }
+        RawT raw;
+        W.get(w.buf ^ 1, threadIdx.x, raw);
+        hop_compute<float, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
     } else {
         RawT raw;
         const int l = (int)threadIdx.x;
@@ -803,8 +757,23 @@ __device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, c
     }
 }
 
+#ifndef TM_WALK_WAVES_F32
+#define TM_WALK_WAVES_F32 3
+#endif
+#ifndef TM_WALK_WAVES_F16
+#define TM_WALK_WAVES_F16 5
+#endif
+#ifndef TM_WALK_WAVES_F16_CG
+#define TM_WALK_WAVES_F16_CG 4
+#endif
+template <int SP, int EPI>
+constexpr int walk_waves()
+{
+    return SP == P32 ? TM_WALK_WAVES_F32 : EPI == EPI_CGUPD ? TM_WALK_WAVES_F16_CG : TM_WALK_WAVES_F16;
+}
+
 template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, bool NT>
-__global__ __launch_bounds__(WSPB, dslash_waves<SP>()) void k_dslash_walk(const DslashArgs A)
+__global__ __launch_bounds__(WSPB, (walk_waves<SP, EPI>())) void k_dslash_walk(const DslashArgs A)
 {
     using RawT = typename RawSel<SP, float>::type;
     __shared__ WalkBuf<SP> W;
@@ -849,17 +818,22 @@ __global__ __launch_bounds__(WSPB, dslash_waves<SP>()) void k_dslash_walk(const 
         cpx<float> acc[12];
 #pragma unroll
         for (int q = 0; q < 12; q++) acc[q] = cpx<float>{0.f, 0.f};
+        // backward t neighbour first: it frees this thread's slot of timeslice
+        // t-1, which then takes timeslice t+1 (the forward t neighbour now and
+        // the next step's spatial neighbours), so nxt is not held in registers
+        // through the other seven neighbours.
+        walk_dir<SP, 3, false, DAG>(A, R, s, W, w, acc);
+        W.put(w.buf ^ 1, threadIdx.x, nxt);
 #pragma unroll 1
-        for (int d = 0; d < 8; d++) {
+        for (int d = 0; d < 7; d++) {
             switch (__builtin_amdgcn_readfirstlane(d)) {
-            case 0: walk_dir<SP, 0, true, DAG>(A, R, s, W, w, nxt, acc); break;
-            case 1: walk_dir<SP, 0, false, DAG>(A, R, s, W, w, nxt, acc); break;
-            case 2: walk_dir<SP, 1, true, DAG>(A, R, s, W, w, nxt, acc); break;
-            case 3: walk_dir<SP, 1, false, DAG>(A, R, s, W, w, nxt, acc); break;
-            case 4: walk_dir<SP, 2, true, DAG>(A, R, s, W, w, nxt, acc); break;
-            case 5: walk_dir<SP, 2, false, DAG>(A, R, s, W, w, nxt, acc); break;
-            case 6: walk_dir<SP, 3, true, DAG>(A, R, s, W, w, nxt, acc); break;
-            default: walk_dir<SP, 3, false, DAG>(A, R, s, W, w, nxt, acc); break;
+            case 0: walk_dir<SP, 0, true, DAG>(A, R, s, W, w, acc); break;
+            case 1: walk_dir<SP, 0, false, DAG>(A, R, s, W, w, acc); break;
+            case 2: walk_dir<SP, 1, true, DAG>(A, R, s, W, w, acc); break;
+            case 3: walk_dir<SP, 1, false, DAG>(A, R, s, W, w, acc); break;
+            case 4: walk_dir<SP, 2, true, DAG>(A, R, s, W, w, acc); break;
+            case 5: walk_dir<SP, 2, false, DAG>(A, R, s, W, w, acc); break;
+            default: walk_dir<SP, 3, true, DAG>(A, R, s, W, w, acc); break;
             }
         }
         const double part = epilogue<SP, EPI, IN2, 0, NT>(A, slot, cb, acc, kappa, a, alpha);
@@ -868,8 +842,6 @@ __global__ __launch_bounds__(WSPB, dslash_waves<SP>()) void k_dslash_walk(const 
             const double v = wave_sum(part);
             if ((threadIdx.x & 63) == 0) A.partial[(size_t)slot * A.ntile + cb / TILE] = v;
         }
-        // timeslice t+1 replaces t-1 (read by this thread only) for the next step
-        W.put(w.buf ^ 1, threadIdx.x, nxt);
         __syncthreads();
     }
 }

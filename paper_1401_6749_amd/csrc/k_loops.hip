@@ -23,6 +23,20 @@ void launch_z4_codes(const Geom &g, uint64_t seed, uint64_t src, uint32_t *codes
     hipLaunchKernelGGL(k_z4_codes, dim3(nblk_of(g), 2), dim3(BLOCK), 0, s, g, seed, src, codes);
 }
 
+__global__ __launch_bounds__(BLOCK) void k_z4_codes_n(Geom g, Z4Sources Z, uint32_t *codes)
+{
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    const int par = blockIdx.y & 1, i = blockIdx.y >> 1;
+    if (cb >= g.vh) return;
+    const Site s = site_of(g, cb, par);
+    codes[((size_t)i * 2 + par) * g.vh + cb] = z4_code(lex_of(g, s), Z.src[i], Z.seed[i]);
+}
+
+void launch_z4_codes(const Geom &g, const Z4Sources &Z, int n, uint32_t *codes, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_z4_codes_n, dim3(nblk_of(g), 2 * n), dim3(BLOCK), 0, s, g, Z, codes);
+}
+
 #define TM_RSQRT2 0.70710678118654752440
 
 __global__ __launch_bounds__(BLOCK) void k_z4_field(Geom g, const uint32_t *codes, int ainv, double a, char *out)
@@ -196,14 +210,18 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
 }
 
 // partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
+// blockIdx.y = source
 template <int SPS>
 __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd,
-                                                 const uint32_t *codes, double *cpart, int nchunk)
+                                                 size_t s_stride, const uint32_t *codes, double *cpart, int nchunk,
+                                                 size_t part_stride)
 {
     __shared__ double lds[(CT / 64) * 32];
     const int t = blockIdx.x / nchunk, chunk = blockIdx.x - t * nchunk;
-    const char *s_fld[2] = {s_even, s_odd};
-    double *dst = cpart + (size_t)blockIdx.x * 288;
+    const int i = blockIdx.y;
+    const char *s_fld[2] = {s_even + (size_t)i * s_stride, s_odd + (size_t)i * s_stride};
+    codes += (size_t)i * 2 * g.vh;
+    double *dst = cpart + (size_t)i * part_stride + (size_t)blockIdx.x * 288;
     double acc[32];
 #define TMK_KIND(K)                                                  \
     contract_kind<K, SPS>(g, G, s_fld, codes, t, chunk, acc);        \
@@ -220,11 +238,13 @@ __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const ch
 #undef TMK_KIND
 }
 
-// raw[kind][t][ab][2] = 2^-1/2 * sum_chunk cpart[t][chunk][kind][ab][2]
-__global__ void k_contract_final(const double *cpart, int nchunk, int lt, double *raw)
+// raw[kind][t][ab][2] = 2^-1/2 * sum_chunk cpart[t][chunk][kind][ab][2]; blockIdx.y = source
+__global__ void k_contract_final(const double *cpart, int nchunk, int lt, RawOuts R, size_t part_stride)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over lt * 288
     if (i >= lt * 288) return;
+    cpart += (size_t)blockIdx.y * part_stride;
+    double *raw = R.p[blockIdx.y];
     const int t = i / 288, e = i - t * 288;
     double s = 0.0;
     for (int c = 0; c < nchunk; c++) s += cpart[((size_t)t * nchunk + c) * 288 + e];
@@ -232,19 +252,31 @@ __global__ void k_contract_final(const double *cpart, int nchunk, int lt, double
     raw[((size_t)kind * lt + t) * 32 + ab] = s * TM_RSQRT2;
 }
 
+size_t contract_part_doubles(const Geom &g) { return (size_t)g.L[3] * contract_nchunk(g) * 288; }
+
+void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
+                     size_t s_stride, const uint32_t *codes, double *cpart, const RawOuts &raw, int n, hipStream_t s)
+{
+    if (n < 1) return;
+    const int nchunk = contract_nchunk(g);
+    const int lt = g.L[3];
+    const size_t ps = contract_part_doubles(g);
+    if (sps == P32)
+        hipLaunchKernelGGL((k_contract<P32>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even, s_odd, s_stride,
+                           codes, cpart, nchunk, ps);
+    else
+        hipLaunchKernelGGL((k_contract<P64>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even, s_odd, s_stride,
+                           codes, cpart, nchunk, ps);
+    const int m = lt * 288;
+    hipLaunchKernelGGL(k_contract_final, dim3((m + 255) / 256, n), dim3(256), 0, s, cpart, nchunk, lt, raw, ps);
+}
+
 void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
                      const uint32_t *codes, double *cpart, double *raw_out, hipStream_t s)
 {
-    const int nchunk = contract_nchunk(g);
-    const int lt = g.L[3];
-    if (sps == P32)
-        hipLaunchKernelGGL((k_contract<P32>), dim3(lt * nchunk), dim3(CT), 0, s, g, gauge, s_even, s_odd, codes,
-                           cpart, nchunk);
-    else
-        hipLaunchKernelGGL((k_contract<P64>), dim3(lt * nchunk), dim3(CT), 0, s, g, gauge, s_even, s_odd, codes,
-                           cpart, nchunk);
-    const int n = lt * 288;
-    hipLaunchKernelGGL(k_contract_final, dim3((n + 255) / 256), dim3(256), 0, s, cpart, nchunk, lt, raw_out);
+    RawOuts R{};
+    R.p[0] = raw_out;
+    launch_contract(sps, g, gauge, s_even, s_odd, 0, codes, cpart, R, 1, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -304,10 +304,10 @@ static void worker_main(tm_server *S)
                 }
                 progressed = true;
             }
-            int slot;
-            while (!br->pending.empty() && (slot = batch_free_slot(b)) >= 0) {
-                batch_fill(b, slot, br->pending.front());
-                br->pending.pop_front();
+            if (!br->pending.empty() && batch_free_slot(b) >= 0) {
+                std::vector<Job *> js(br->pending.begin(), br->pending.end());
+                const int m = batch_fill_many(b, js.data(), (int)js.size());
+                for (int i = 0; i < m; i++) br->pending.pop_front();
                 progressed = true;
             }
             if (batch_active(b) > 0) {

@@ -105,7 +105,10 @@ struct Batch {
     char *p = nullptr, *u = nullptr, *t = nullptr, *x = nullptr, *r = nullptr;
     char *x64 = nullptr, *b64 = nullptr;
     uint32_t *codes = nullptr;
-    char *FA = nullptr, *FB = nullptr, *FC = nullptr;  // FP64 full-field scratch [even | odd]
+    char *FA = nullptr, *FB = nullptr, *FC = nullptr;  // scratch: FP64 full field [even | odd], or per-slot halves
+    int wpp = tmk::P64;       // precision of the per-slot scratch halves
+    size_t wpitch = 0;        // their slot pitch
+    int wslots = 1;           // slots a run may span
     double *partial = nullptr;
     int nblk = 0;
     double *cpart = nullptr;
@@ -131,6 +134,9 @@ int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk
                  const Mem *mem = nullptr);
 void batch_destroy(Batch *b);
 int batch_fill(Batch *b, int slot, Job *j);
+// place up to n jobs into free slots (noise solves with equal kappa, a in
+// consecutive slots are prepared together); returns the number placed
+int batch_fill_many(Batch *b, Job *const *jobs, int n);
 int batch_launch_chunk(Batch *b);
 // after the chunk's event completed: reliable updates and harvests; fills
 // *finished with the jobs that completed.  Returns tm_status.

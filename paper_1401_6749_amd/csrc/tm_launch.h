@@ -22,11 +22,20 @@ void launch_cg_beta(SlotState *st, const double *partial, int nslot, int nblk, h
 // p = r + beta p for running slots (sp = p precision, xr = r precision)
 void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot,
                      SlotState *st, int nslot, int swz, hipStream_t s);
-// start a slot: rr0 = sum(partial[0..nblk)), status RUNNING (or CONVERGED if rr0 == 0)
+// start n consecutive slots: rr0 = sum of the slot's nblk partials, status
+// RUNNING (or CONVERGED if rr0 == 0); parameters per slot
+struct SlotStartParams {
+    double kappa[MAX_SLOTS], a[MAX_SLOTS], tol2[MAX_SLOTS], delta2[MAX_SLOTS];
+    int max_iter[MAX_SLOTS];
+    int mixed;
+};
+void launch_slot_start(SlotState *st, const double *partial, int nblk, const SlotStartParams &P, int n,
+                       hipStream_t s);
 void launch_slot_start(SlotState *st, const double *partial, int nblk, double kappa, double a, double tol2,
                        int max_iter, double delta2, int mixed, hipStream_t s);
-// after an FP64 reliable update: rr_true = sum(partial); decide convergence, set beta
-void launch_reliable_finish(SlotState *st, const double *partial, int nblk, hipStream_t s);
+// after FP64 reliable updates of n consecutive slots: rr_true = sum(partial);
+// decide convergence, set beta
+void launch_reliable_finish(SlotState *st, const double *partial, int nblk, int n, hipStream_t s);
 // out[k] = sum(partial[k*nblk .. (k+1)*nblk)) for k < n (fixed order)
 void launch_reduce(const double *partial, int nblk, int n, double *out, hipStream_t s);
 
@@ -34,8 +43,9 @@ void launch_reduce(const double *partial, int nblk, int n, double *out, hipStrea
 void launch_convert(int pin, int pout, const Geom &g, const char *in, size_t in_slot, char *out, size_t out_slot,
                     int nslot, hipStream_t s);
 void launch_zero(int p, const Geom &g, char *f, size_t slot, int nslot, hipStream_t s);
-// x64 += x32; x32 = 0
-void launch_accum_x(const Geom &g, char *x64, const char *x32_in, char *x32_zero, hipStream_t s);
+// x64 += x32; x32 = 0 (if x32_zero), n consecutive slots with strides s64, s32
+void launch_accum_x(const Geom &g, char *x64, size_t s64, const char *x32_in, char *x32_zero, size_t s32, int n,
+                    hipStream_t s);
 // per-tile (64 sites) |f|^2 partials of one FP64 half field
 void launch_norm_partial(const Geom &g, const char *f, double *partial, hipStream_t s);
 // out = c * in with c per chirality: A^-1 (mode 1) or identity (mode 0), FP64
@@ -44,6 +54,11 @@ void launch_site_diag(const Geom &g, int mode, double a, const char *in, char *o
 // ---- noise ----
 // Z4 codes of both parities: codes[par*vh + cb]
 void launch_z4_codes(const Geom &g, uint64_t seed, uint64_t src, uint32_t *codes, hipStream_t s);
+// the same for n sources (n <= MAX_SLOTS) into codes + i * 2 * vh
+struct Z4Sources {
+    uint64_t seed[MAX_SLOTS], src[MAX_SLOTS];
+};
+void launch_z4_codes(const Geom &g, const Z4Sources &Z, int n, uint32_t *codes, hipStream_t s);
 // eta of one parity as an FP64 half field (times A^-1 when ainv != 0)
 void launch_z4_field(const Geom &g, const uint32_t *codes_par, int ainv, double a, char *out, hipStream_t s);
 // canonical FP64 layout [V][4][3][2]
@@ -55,6 +70,15 @@ int contract_nchunk(const Geom &g);
 // or FP32 (sps; gauge must be that precision's link array), accumulation FP64
 void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
                      const uint32_t *codes, double *cpart, double *raw_out, hipStream_t s);
+// n sources at once (n <= MAX_SLOTS): source i has s_even + i * s_stride,
+// s_odd + i * s_stride, codes + i * 2 * vh, partials cpart + i * contract_part_doubles
+// and output raw_out[i]
+struct RawOuts {
+    double *p[MAX_SLOTS];
+};
+size_t contract_part_doubles(const Geom &g);
+void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
+                     size_t s_stride, const uint32_t *codes, double *cpart, const RawOuts &raw, int n, hipStream_t s);
 // raw [n][9][T][16][2] -> ops [n][90][T][2]; gtab: [16][4] (col | phase << 2)
 void launch_project(int n, int lt, const double *raw, double *ops, const int *gtab_host, hipStream_t s);
 // TSM combination over per-source ops

@@ -246,3 +246,26 @@ def test_lp_noise_path_matched_iterations(oracle, half):
     for j in range(3):
         assert GU.relerr(r["raw_lp"][j], ref["lp_raw"][j]) < tol, (j, GU.relerr(r["raw_lp"][j], ref["lp_raw"][j]))
     assert r["stats"]["lp_iters"] == 15
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("half", ["f16", "bf16"])
+def test_lp_loops_batch_invariant_and_repeatable(half):
+    """LP noise solves (half-precision CG, FP32 preparation and contraction
+    in runs of slots) give the same bits for every source alone, in a batch
+    of 12 and on a repeat: no dependence on run length, slot or timing."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (8, 8, 8, 16)
+    g = GU.load(dims, inputs.gauge_field(dims, 11))
+    out = []
+    for batch in (1, 12, 12):
+        P = tm.tsm_params(0.1636, 0.0033, 7, 3, 20, hp=tm.solver_params("mixed", tol=1e-10),
+                          lp=tm.solver_params("lp", tol=1e-2, half=half), batch=batch)
+        out.append(tm.tm_loops_tsm(ctx, g, P, dims[3], want_raw=True))
+    for r in out[1:]:
+        assert np.array_equal(r["raw_lp"], out[0]["raw_lp"])
+        assert np.array_equal(r["raw_hp"], out[0]["raw_hp"])
+        assert np.array_equal(r["est"], out[0]["est"])
+        assert r["stats"]["lp_iters"] == out[0]["stats"]["lp_iters"]
