@@ -761,7 +761,7 @@ __device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, c
 #define TM_WALK_WAVES_F32 3
 #endif
 #ifndef TM_WALK_WAVES_F16
-#define TM_WALK_WAVES_F16 5
+#define TM_WALK_WAVES_F16 4
 #endif
 #ifndef TM_WALK_WAVES_F16_CG
 #define TM_WALK_WAVES_F16_CG 4
