@@ -38,7 +38,7 @@ WORKLOADS = {
     "tsm-24c48": dict(dims=(24, 24, 24, 48), kappa=0.1636, a=0.0033, n_hp=24, n_lp=500, half="f16", batch=12,
                       gauge_seed=3, noise_seed=103),
 }
-LINK_BYTES = {"f64": 96, "f32": 48, "f16": 24, "bf16": 24}
+LINK_BYTES = {"f64": 96, "f32": 48, "f16": 36, "bf16": 36}
 SPINOR_BYTES = {"f64": 192, "f32": 96, "f16": 52, "bf16": 52}
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f16_traffic.json")
@@ -73,6 +73,97 @@ def event_time(torch, fn, n, warm=3):
     return e0.elapsed_time(e1) / 1e3 / n
 
 
+def slot_pitch(nbytes: int) -> int:
+    """Pitch the solver uses between the fields of consecutive right-hand sides."""
+    return (nbytes + 255) // 256 * 256 + 17 * 256
+
+
+def measure_roofline(torch, tm, inputs, ctx, g, W, workload):
+    """The dominant kernel: the FP16 hop over `batch` right-hand sides laid out
+    with the solver's slot pitch (the LDS timeslice-walk kernel), timed with
+    HIP events on the stream it is launched on, and the copy ceiling."""
+    dims = W["dims"]
+    vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    prec = W["half"]
+    nrhs = W["batch"]
+    fb = tm.tm_field_bytes(g, prec, True)
+    pitch = slot_pitch(fb)
+    fin = torch.zeros(nrhs * pitch, dtype=torch.uint8, device="cuda")
+    psi = tm.canonical_to_torch(inputs.random_spinor(dims, 1)[None])
+    for r in range(nrhs):
+        tm.tm_field_import(ctx, g, prec, 1, psi, fin[r * pitch:r * pitch + fb])
+    fout = torch.zeros_like(fin)
+    n_calls = 20
+    t_call = event_time(torch, lambda: tm.tm_dslash_ex(ctx, g, "hop", W["kappa"], W["a"], prec, nrhs, fin, pitch,
+                                                        fout, pitch), n_calls)
+    t_launch = t_call / 2  # one launch per output parity
+    alg_bytes = vh * (8 * LINK_BYTES[prec] + nrhs * 2 * SPINOR_BYTES[prec])
+    achieved = alg_bytes / t_launch / 1e9
+    # copy ceiling with the library's streaming copy kernel (1 GiB)
+    nb = 1 << 30
+    ca = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    cb = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    t_copy = event_time(torch, lambda: tm.tm_stream_copy(ctx, ca, cb, nb), 20)
+    copy_gbs = 2 * nb / t_copy / 1e9
+    del ca, cb, fin, fout
+    traffic = None
+    khash = kernel_hash()
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == khash and tr.get("workload") == workload and tr.get("nrhs") == nrhs:
+            traffic = tr.get("hbm_bytes_per_launch")
+    log(f"dslash {prec} x{nrhs}: {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s; copy {copy_gbs:.0f} GB/s")
+    return {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "kernel": f"k_dslash_walk {prec} hop, {nrhs} RHS per launch, {dims[0]}^3x{dims[3]}",
+        "alg_bytes_per_launch": alg_bytes, "launch_us": round(t_launch * 1e6, 2),
+        "copy_ceiling_GBs": round(copy_gbs, 1), "kernel_hash": khash,
+    }
+
+
+def write_traffic(fetch_db: str, write_db: str, workload: str) -> None:
+    """Per-launch HBM bytes of the roofline kernel from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for the 1 GiB streaming copy (which reads and writes exactly 1 GiB)."""
+    import sqlite3
+
+    W = WORKLOADS[workload]
+
+    def per_dispatch(db, counter):
+        cur = sqlite3.connect(db).cursor()
+        rows = cur.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                           (counter,)).fetchall()
+        copy = [v for n, v in rows if "k_stream_copy" in n]
+        kern = [v for n, v in rows if "k_dslash_walk<2, false, 0, false, false" in n]
+        if not copy or not kern:
+            raise SystemExit(f"{db}: no {counter} rows for the copy or the FP16 hop kernel")
+        return sum(copy) / len(copy), sum(kern) / len(kern), len(kern)
+
+    cf, kf, nf = per_dispatch(fetch_db, "FETCH_SIZE")
+    cw, kw, nw = per_dispatch(write_db, "WRITE_SIZE")
+    f_fetch = (1 << 30) / (cf * 1024.0)
+    f_write = (1 << 30) / (cw * 1024.0)
+    fetch = kf * 1024.0 * f_fetch
+    write = kw * 1024.0 * f_write
+    out = {
+        "workload": workload, "nrhs": W["batch"], "kernel_hash": kernel_hash(),
+        "kernel": "k_dslash_walk FP16 hop (uniform parameters), one launch per output parity",
+        "fetch_scale": round(f_fetch, 4), "write_scale": round(f_write, 4),
+        "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
+        "hbm_bytes_per_launch": round(fetch + write), "dispatches": [nf, nw],
+        "commands": ["rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --roofline-only",
+                     "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write -- python3 bench.py --roofline-only",
+                     "python3 bench.py --traffic-from gpurun_out/pmc_fetch/fetch_results.db "
+                     "gpurun_out/pmc_write/write_results.db"],
+    }
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,7 +173,15 @@ def main():
     ap.add_argument("--plain-sources", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the copy calibration and the roofline kernel (for counter runs)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write the roofline kernel's HBM traffic from two rocprofv3 --pmc databases "
+                         "(FETCH_SIZE, WRITE_SIZE) of --roofline-only runs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(args.traffic_from[0], args.traffic_from[1], args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the whole lattice is resident on a single MI355X and this build "
               f"has no multi-GPU path (requested --gpus {args.gpus}).", file=sys.stderr)
@@ -103,6 +202,11 @@ def main():
     U = inputs.gauge_field(dims, W["gauge_seed"])
     g = tm.tm_load_gauge(ctx, dims, U, -1, ("f32", "f16", "bf16"))
     log(f"gauge {dims} ready in {time.time() - t0:.1f}s")
+    if args.roofline_only:
+        print(json.dumps({"roofline": measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)}), flush=True)
+        tm.tm_free_gauge(ctx, g)
+        tm.tm_destroy(ctx)
+        return
 
     hp = tm.solver_params("mixed", tol=1e-10, delta=0.1)
     lp = tm.solver_params("lp", tol=1e-2, half=W["half"])
@@ -154,43 +258,7 @@ def main():
         log(f"plain FP64: {plain_rate:.2f} sources/s; TSM equal-error speedup local "
             f"{plain['tsm_effective_speedup_local_median']:.1f}x deriv {plain['tsm_effective_speedup_deriv_median']:.1f}x")
 
-    # ---- roofline of the dominant kernel: FP16 hop with `batch` RHS ----
-    prec = W["half"]
-    nrhs = W["batch"]
-    fb = tm.tm_field_bytes(g, prec, True)
-    fin = torch.empty(nrhs * fb, dtype=torch.uint8, device="cuda")
-    psi = tm.canonical_to_torch(inputs.random_spinor(dims, 1)[None])
-    for r in range(nrhs):
-        tm.tm_field_import(ctx, g, prec, 1, psi, fin[r * fb:(r + 1) * fb])
-    fout = torch.empty_like(fin)
-    n_calls = 20
-    t_call = event_time(torch, lambda: tm.tm_dslash(ctx, g, "hop", W["kappa"], W["a"], prec, nrhs, fin, fout),
-                        n_calls)
-    t_launch = t_call / 2  # one launch per output parity
-    alg_bytes = vh * (8 * LINK_BYTES[prec] + nrhs * 2 * SPINOR_BYTES[prec])
-    achieved = alg_bytes / t_launch / 1e9
-    # copy ceiling with the library's streaming copy kernel
-    nb = 1 << 30
-    ca = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    cb = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    t_copy = event_time(torch, lambda: tm.tm_stream_copy(ctx, ca, cb, nb), 20)
-    copy_gbs = 2 * nb / t_copy / 1e9
-    del ca, cb, fin, fout
-    traffic = None
-    khash = kernel_hash()
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("kernel_hash") == khash and tr.get("workload") == args.workload and tr.get("nrhs") == nrhs:
-            traffic = tr.get("hbm_bytes_per_launch")
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-        "kernel": f"k_dslash {prec} hop, {nrhs} RHS per launch, {dims[0]}^3x{lt}",
-        "alg_bytes_per_launch": alg_bytes, "launch_us": round(t_launch * 1e6, 2),
-        "copy_ceiling_GBs": round(copy_gbs, 1), "kernel_hash": khash,
-    }
-    log(f"dslash {prec} x{nrhs}: {t_launch * 1e6:.1f} us/launch, {achieved:.0f} GB/s; copy {copy_gbs:.0f} GB/s")
+    roofline = measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)
 
     # ---- CPU oracle on a bounded sample (one LP source at the same lattice) ----
     cpu = None
@@ -236,7 +304,9 @@ def main():
             "n_hp": W["n_hp"],
             "n_lp": W["n_lp"],
             "hp": "mixed FP32 CG with FP64 reliable updates, tol 1e-10",
-            "lp": f"{W['half']} storage, FP32 math, truncated at |r|/|r0| = 1e-2",
+            "lp": (f"{W['half']} storage; Dslash: " + ("f16 spin projection, f16 x f16 products summed in FP32"
+                                                       if W["half"] == "f16" else "FP32 arithmetic")
+                   + "; FP32 vector updates and preparation; truncated at |r|/|r0| = 1e-2"),
             "rhs_per_launch": W["batch"],
             "parallelism": "single GPU, whole lattice resident",
         },
