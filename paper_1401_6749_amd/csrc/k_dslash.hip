@@ -274,18 +274,15 @@ __device__ __forceinline__ void raw_setup(RawZ4<T> &z, double den, double a)
 }
 
 // ---------------------------------------------------------------------------
-// FP16 hop on packed operands.  A stored spinor component and a stored link
-// entry are each one 32-bit word holding a complex number as two halves
-// (re low, im high).  The spin projection adds two stored components in
-// packed FP16 (one rounding to FP16, the same size as the storage rounding);
-// the colour transport multiplies FP16 link entries by FP16 half-spinor
-// entries with the two-term FP16 dot product, whose products are exact in
-// FP32 and whose sums are FP32; the neighbour's per-site scale enters in the
-// FP32 accumulation.  Written with vector types and the dot-product builtin
-// (no inline assembly), so the compiler sees every instruction and inserts
-// the wait states the dot-product results need before other instructions
-// read them; it folds the signs and swaps of the projection into operand
-// modifiers of v_pk_add_f16.
+// FP16 hop with FP32 arithmetic on the stored halves.  A stored spinor
+// component and a stored link entry are each one 32-bit word holding a
+// complex number as two halves (re low, im high).  Every operation is an FP32
+// fused multiply-add whose FP16 operands are widened exactly inside the
+// instruction (v_fma_mix_f32), so neither the neighbour spinor nor the link
+// is decoded into registers first: the spin projection is one FP32 add per
+// real component and the colour transport four FP32 multiply-adds per complex
+// product, the same arithmetic as the FP32 kernel.  The neighbour's per-site
+// scale enters in the FP32 accumulation.
 // ---------------------------------------------------------------------------
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
@@ -295,94 +292,48 @@ __device__ __forceinline__ h2 as_h2(uint32_t x)
     __builtin_memcpy(&r, &x, 4);
     return r;
 }
-__device__ __forceinline__ h2 mul_i(h2 b) { return (h2){-b.y, b.x}; }  // i b
-__device__ __forceinline__ h2 swap_h(h2 b) { return __builtin_shufflevector(b, b, 1, 0); }
-__device__ __forceinline__ h2 conj_h(h2 b)  // flip the sign bit of the high half
-{
-    uint32_t x;
-    __builtin_memcpy(&x, &b, 4);
-    return as_h2(x ^ 0x80000000u);
-}
+__device__ __forceinline__ float lo_f(uint32_t x) { return (float)as_h2(x).x; }
+__device__ __forceinline__ float hi_f(uint32_t x) { return (float)as_h2(x).y; }
 
-// packed half spinor of colour c for the projector (1 + S g_mu), from stored words p[k], k = 3*spin + colour
+// sc times the half spinor of colour c for the projector (1 + S g_mu), FP32,
+// from the stored words p[3*spin + colour]: two mixed-precision FMAs per real
+// component, so the neighbour's scale costs nothing later
 template <int MU, int S>
-__device__ __forceinline__ void project_pk(const uint32_t p[12], int c, h2 &h0, h2 &h1)
+__device__ __forceinline__ void project_pk(const uint32_t p[12], int c, float sc, cpx<float> &h0, cpx<float> &h1)
 {
-    const h2 p0 = as_h2(p[c]), p1 = as_h2(p[3 + c]), p2 = as_h2(p[6 + c]), p3 = as_h2(p[9 + c]);
-    if (MU == 0) {
-        h0 = S > 0 ? p0 - mul_i(p3) : p0 + mul_i(p3);
-        h1 = S > 0 ? p1 - mul_i(p2) : p1 + mul_i(p2);
-    } else if (MU == 1) {
-        h0 = S > 0 ? p0 - p3 : p0 + p3;
-        h1 = S > 0 ? p1 + p2 : p1 - p2;
-    } else if (MU == 2) {
-        h0 = S > 0 ? p0 - mul_i(p2) : p0 + mul_i(p2);
-        h1 = S > 0 ? p1 + mul_i(p3) : p1 - mul_i(p3);
-    } else {
-        h0 = S > 0 ? p0 + p2 : p0 - p2;
-        h1 = S > 0 ? p1 + p3 : p1 - p3;
+    const uint32_t p0 = p[c], p1 = p[3 + c], p2 = p[6 + c], p3 = p[9 + c];
+    const float s = S > 0 ? sc : -sc;
+    if (MU == 0) {  // p0 - i S p3, p1 - i S p2
+        h0 = {fmaf(sc, lo_f(p0), fmaf(s, hi_f(p3), 0.f)), fmaf(sc, hi_f(p0), fmaf(-s, lo_f(p3), 0.f))};
+        h1 = {fmaf(sc, lo_f(p1), fmaf(s, hi_f(p2), 0.f)), fmaf(sc, hi_f(p1), fmaf(-s, lo_f(p2), 0.f))};
+    } else if (MU == 1) {  // p0 - S p3, p1 + S p2
+        h0 = {fmaf(sc, lo_f(p0), fmaf(-s, lo_f(p3), 0.f)), fmaf(sc, hi_f(p0), fmaf(-s, hi_f(p3), 0.f))};
+        h1 = {fmaf(sc, lo_f(p1), fmaf(s, lo_f(p2), 0.f)), fmaf(sc, hi_f(p1), fmaf(s, hi_f(p2), 0.f))};
+    } else if (MU == 2) {  // p0 - i S p2, p1 + i S p3
+        h0 = {fmaf(sc, lo_f(p0), fmaf(s, hi_f(p2), 0.f)), fmaf(sc, hi_f(p0), fmaf(-s, lo_f(p2), 0.f))};
+        h1 = {fmaf(sc, lo_f(p1), fmaf(-s, hi_f(p3), 0.f)), fmaf(sc, hi_f(p1), fmaf(s, lo_f(p3), 0.f))};
+    } else {  // p0 + S p2, p1 + S p3
+        h0 = {fmaf(sc, lo_f(p0), fmaf(s, lo_f(p2), 0.f)), fmaf(sc, hi_f(p0), fmaf(s, hi_f(p2), 0.f))};
+        h1 = {fmaf(sc, lo_f(p1), fmaf(s, lo_f(p3), 0.f)), fmaf(sc, hi_f(p1), fmaf(s, hi_f(p3), 0.f))};
     }
 }
 
-// w = U h (FWD) or U^dagger h from packed link words u[3*row+col] and packed h
+// w = U h (FWD) or U^dagger h from the link words u[3*row + col]
 template <bool FWD>
-__device__ __forceinline__ void transport_pk(const uint32_t u[9], const h2 h[3], float wr[3], float wi[3])
+__device__ __forceinline__ void transport_pk(const uint32_t u[9], const cpx<float> h[3], float wr[3], float wi[3])
 {
-    h2 hr[3], hi[3];
-#pragma unroll
-    for (int b = 0; b < 3; b++) {
-        // FWD: re = u.re h.re - u.im h.im, im = u.re h.im + u.im h.re
-        // BWD (conj u): re = u.re h.re + u.im h.im, im = u.re h.im - u.im h.re
-        hr[b] = FWD ? conj_h(h[b]) : h[b];
-        hi[b] = FWD ? swap_h(h[b]) : conj_h(swap_h(h[b]));
-    }
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         float re = 0.f, im = 0.f;
 #pragma unroll
         for (int b = 0; b < 3; b++) {
-            const h2 ue = as_h2(FWD ? u[3 * a + b] : u[3 * b + a]);
-            re = __builtin_amdgcn_fdot2(ue, hr[b], re, false);
-            im = __builtin_amdgcn_fdot2(ue, hi[b], im, false);
+            const uint32_t e = FWD ? u[3 * a + b] : u[3 * b + a];
+            const float ur = lo_f(e), ui = FWD ? hi_f(e) : -hi_f(e);
+            re = fmaf(ur, h[b].re, fmaf(-ui, h[b].im, re));
+            im = fmaf(ur, h[b].im, fmaf(ui, h[b].re, im));
         }
         wr[a] = re;
         wi[a] = im;
-    }
-}
-
-// acc += sc * (the four spin rows rebuilt from w0 = (wr0, wi0), w1 = (wr1, wi1)) as in accum
-template <int MU, int S>
-__device__ __forceinline__ void accum_pk(cpx<float> acc[12], const float wr0[3], const float wi0[3],
-                                         const float wr1[3], const float wi1[3], float sc)
-{
-    const float s = S > 0 ? sc : -sc;
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        acc[c].re = fmaf(sc, wr0[c], acc[c].re);
-        acc[c].im = fmaf(sc, wi0[c], acc[c].im);
-        acc[3 + c].re = fmaf(sc, wr1[c], acc[3 + c].re);
-        acc[3 + c].im = fmaf(sc, wi1[c], acc[3 + c].im);
-        if (MU == 0) {  // rows 2,3 = iS w1, iS w0
-            acc[6 + c].re = fmaf(-s, wi1[c], acc[6 + c].re);
-            acc[6 + c].im = fmaf(s, wr1[c], acc[6 + c].im);
-            acc[9 + c].re = fmaf(-s, wi0[c], acc[9 + c].re);
-            acc[9 + c].im = fmaf(s, wr0[c], acc[9 + c].im);
-        } else if (MU == 1) {  // S w1, -S w0
-            acc[6 + c].re = fmaf(s, wr1[c], acc[6 + c].re);
-            acc[6 + c].im = fmaf(s, wi1[c], acc[6 + c].im);
-            acc[9 + c].re = fmaf(-s, wr0[c], acc[9 + c].re);
-            acc[9 + c].im = fmaf(-s, wi0[c], acc[9 + c].im);
-        } else if (MU == 2) {  // iS w0, -iS w1
-            acc[6 + c].re = fmaf(-s, wi0[c], acc[6 + c].re);
-            acc[6 + c].im = fmaf(s, wr0[c], acc[6 + c].im);
-            acc[9 + c].re = fmaf(s, wi1[c], acc[9 + c].re);
-            acc[9 + c].im = fmaf(-s, wr1[c], acc[9 + c].im);
-        } else {  // S w0, S w1
-            acc[6 + c].re = fmaf(s, wr0[c], acc[6 + c].re);
-            acc[6 + c].im = fmaf(s, wi0[c], acc[6 + c].im);
-            acc[9 + c].re = fmaf(s, wr1[c], acc[9 + c].re);
-            acc[9 + c].im = fmaf(s, wi1[c], acc[9 + c].im);
-        }
     }
 }
 
@@ -401,13 +352,20 @@ __device__ __forceinline__ void hop_compute_pk(const DslashArgs &A, __amdgpu_buf
     uint32_t u[9];
     load_link_words(gauge, vh, FWD ? A.out_par : 1 - A.out_par, MU, FWD ? s.cb : n, u);
     if (MU == 3 && A.g.tbc < 0 && s.t == (FWD ? A.g.L[3] - 1 : 0)) sc = -sc;
-    h2 h0[3], h1[3];
+    cpx<float> h0[3], h1[3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) project_pk<MU, S>(p, c, h0[c], h1[c]);
-    float wr0[3], wi0[3], wr1[3], wi1[3];
-    transport_pk<FWD>(u, h0, wr0, wi0);
-    transport_pk<FWD>(u, h1, wr1, wi1);
-    accum_pk<MU, S>(acc, wr0, wi0, wr1, wi1, sc);
+    for (int c = 0; c < 3; c++) project_pk<MU, S>(p, c, sc, h0[c], h1[c]);
+    cpx<float> w[6];
+    {
+        float wr[3], wi[3];
+        transport_pk<FWD>(u, h0, wr, wi);
+#pragma unroll
+        for (int a = 0; a < 3; a++) w[a] = cpx<float>{wr[a], wi[a]};
+        transport_pk<FWD>(u, h1, wr, wi);
+#pragma unroll
+        for (int a = 0; a < 3; a++) w[3 + a] = cpx<float>{wr[a], wi[a]};
+    }
+    accum<float, MU, S>(acc, w);
 }
 
 // One neighbour n of site s from its loaded storage form raw: forward x+mu
