@@ -639,9 +639,30 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
 // neighbour is that of k_dslash; the backward t neighbour is summed first.
 // ---------------------------------------------------------------------------
 constexpr int WSPB = 256;
+// largest chunk (threads per block) per storage precision: FP64 spinors are
+// 192 B, so its two LDS buffers hold 128 sites
+template <int SP>
+constexpr int walk_max()
+{
+    return SP == P64 ? 128 : WSPB;
+}
 
 template <int SP>
 struct WalkBuf;
+template <>
+struct WalkBuf<P64> {
+    u32x4 q[2][12][128];
+    __device__ __forceinline__ void get(int b, int d, Raw<P64, double> &r) const
+    {
+#pragma unroll
+        for (int k = 0; k < 12; k++) r.q[k] = as_d2(q[b][k][d]);
+    }
+    __device__ __forceinline__ void put(int b, int d, const Raw<P64, double> &r)
+    {
+#pragma unroll
+        for (int k = 0; k < 12; k++) __builtin_memcpy(&q[b][k][d], &r.q[k], 16);
+    }
+};
 template <>
 struct WalkBuf<P32> {
     u32x4 q[2][6][WSPB];
@@ -687,14 +708,15 @@ struct WalkPos {
 // other LDS buffer (t-1 until the backward neighbour is done, t+1 after).
 template <int SP, int MU, bool FWD, bool DAG>
 __device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, const Site &s, const WalkBuf<SP> &W,
-                                         const WalkPos &w, cpx<float> acc[12])
+                                         const WalkPos &w, cpx<typename Real<SP>::T> acc[12])
 {
-    using RawT = typename RawSel<SP, float>::type;
+    using T = typename Real<SP>::T;
+    using RawT = typename RawSel<SP, T>::type;
     const int n = nbr<MU, FWD ? 1 : -1>(A.g, s);
     if constexpr (MU == 3) {
         RawT raw;
         W.get(w.buf ^ 1, threadIdx.x, raw);
-        hop_compute<float, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
+        hop_compute<T, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
     } else {
         RawT raw;
         const int l = (int)threadIdx.x;
@@ -711,10 +733,13 @@ __device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, c
         }
         if (in) W.get(w.buf, d, raw);
         else raw.load(R.in, 0, A.g.vh, n);
-        hop_compute<float, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
+        hop_compute<T, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
     }
 }
 
+#ifndef TM_WALK_WAVES_F64
+#define TM_WALK_WAVES_F64 2
+#endif
 #ifndef TM_WALK_WAVES_F32
 #define TM_WALK_WAVES_F32 3
 #endif
@@ -727,13 +752,16 @@ __device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, c
 template <int SP, int EPI>
 constexpr int walk_waves()
 {
-    return SP == P32 ? TM_WALK_WAVES_F32 : EPI == EPI_CGUPD ? TM_WALK_WAVES_F16_CG : TM_WALK_WAVES_F16;
+    return SP == P64 ? TM_WALK_WAVES_F64
+           : SP == P32 ? TM_WALK_WAVES_F32
+                       : EPI == EPI_CGUPD ? TM_WALK_WAVES_F16_CG : TM_WALK_WAVES_F16;
 }
 
 template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, bool NT>
-__global__ __launch_bounds__(WSPB, (walk_waves<SP, EPI>())) void k_dslash_walk(const DslashArgs A)
+__global__ __launch_bounds__(walk_max<SP>(), (walk_waves<SP, EPI>())) void k_dslash_walk(const DslashArgs A)
 {
-    using RawT = typename RawSel<SP, float>::type;
+    using T = typename Real<SP>::T;
+    using RawT = typename RawSel<SP, T>::type;
     __shared__ WalkBuf<SP> W;
     int sb, slot;
     if (!map_block(A.nblk_site, A.nslot, A.swz, sb, slot, A.gouter != 0)) return;
@@ -773,9 +801,9 @@ __global__ __launch_bounds__(WSPB, (walk_waves<SP, EPI>())) void k_dslash_walk(c
         nxt.load(R.in, 0, vh, ((t + 1) % lt) * g.st + o);
         const WalkPos w{k & 1, yy, zz};
         const Site s = site_of(g, cb, A.out_par);
-        cpx<float> acc[12];
+        cpx<T> acc[12];
 #pragma unroll
-        for (int q = 0; q < 12; q++) acc[q] = cpx<float>{0.f, 0.f};
+        for (int q = 0; q < 12; q++) acc[q] = cpx<T>{(T)0, (T)0};
         // backward t neighbour first: it frees this thread's slot of timeslice
         // t-1, which then takes timeslice t+1 (the forward t neighbour now and
         // the next step's spatial neighbours), so nxt is not held in registers
@@ -847,7 +875,7 @@ inline int lanes_per_site(int nslot)
 // 64-site tile (cy = Ly, or cy * Lx/2 a multiple of 64); the fewest halo
 // neighbours per site (2/cy + 2/cz, no term for a dimension the chunk spans),
 // then the largest chunk.  False if no shape fits.
-inline bool walk_chunk(const Geom &g, int &cy, int &cz)
+inline bool walk_chunk(const Geom &g, int maxcs, int &cy, int &cz)
 {
     double best = 1e30;
     int bs = 0;
@@ -856,7 +884,7 @@ inline bool walk_chunk(const Geom &g, int &cy, int &cz)
         for (int z = 1; z <= g.L[2]; z++) {
             if (g.L[2] % z) continue;
             const int cs = y * z * g.lxh;
-            if (cs > WSPB || cs % 64) continue;
+            if (cs > maxcs || cs % 64) continue;
             if (y != g.L[1] && (y * g.lxh) % 64) continue;
             const double halo = (y < g.L[1] ? 2.0 / y : 0.0) + (z < g.L[2] ? 2.0 / z : 0.0);
             if (halo < best - 1e-12 || (halo < best + 1e-12 && cs > bs)) {
@@ -880,16 +908,15 @@ inline int lds_twalk()
 template <int SP, bool DAG, int EPI, bool IN2>
 static bool launch_walk(DslashArgs A, hipStream_t s)
 {
-    if constexpr (SP == P64) {
-        return false;
-    } else {
+    {
         int tw = lds_twalk();
-        const uint64_t field = (uint64_t)A.g.vh * (SP == P32 ? 96 : 52);
-        if (tw < 1 || field >= (1ull << 32) || !walk_chunk(A.g, A.wcy, A.wcz)) return false;
+        const uint64_t field = (uint64_t)A.g.vh * (SP == P64 ? 192 : SP == P32 ? 96 : 52);
+        if (tw < 1 || field >= (1ull << 32) || !walk_chunk(A.g, walk_max<SP>(), A.wcy, A.wcz)) return false;
         while (A.g.L[3] % tw) tw--;
         A.twalk = tw;
         A.in_span = (uint32_t)field;
-        A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P32 ? 48 : 36), 0xFFFFFFFFull);
+        A.gauge_span = (uint32_t)std::min<uint64_t>(
+            (uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : SP == P32 ? 48 : 36), 0xFFFFFFFFull);
         static const int gouter = env_knob("TM_GROUP_OUTER", 0);
         A.gouter = gouter;
         const int cs = A.wcy * A.wcz * A.g.lxh;
