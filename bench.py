@@ -164,6 +164,138 @@ def write_traffic(fetch_db: str, write_db: str, workload: str) -> None:
     print(json.dumps(out))
 
 
+def op_errors(tm, np, test, ref):
+    """Per-operator relative error ||L_test - L_ref|| / ||L_ref|| over (t, source)
+    of raw spin matrices (n, 9, T, 4, 4), summarised per operator class."""
+    a = tm.tm_project_loops(test)
+    b = tm.tm_project_loops(ref)
+    num = np.sqrt((np.abs(a - b) ** 2).sum(axis=(0, 2)))
+    den = np.sqrt((np.abs(b) ** 2).sum(axis=(0, 2)))
+    e = np.where(den > 0, num / np.where(den > 0, den, 1), 0.0)
+    out = {}
+    for name, sl in (("local", slice(0, 16)), ("deriv", slice(16, 80)), ("sym", slice(80, 90))):
+        out[name] = {"median": float(np.median(e[sl])), "max": float(e[sl].max())}
+    return out
+
+
+def precision_segment(tm, np, ctx, g, W, n_hp=4, n_lp=12):
+    """Loop error of the precision paths against the FP64 path (itself pinned to
+    the oracle at 1e-10) for the same source ids and stopping criteria:
+    mixed HP vs FP64 HP at 1e-10; FP16 and BF16 LP vs FP64 LP at 1e-2."""
+    lt = W["dims"][3]
+    f64 = tm.solver_params("f64", tol=1e-10)
+    ref = tm.tm_loops_tsm(ctx, g, tm.tsm_params(W["kappa"], W["a"], W["noise_seed"], n_hp, n_lp, hp=f64,
+                                                lp=tm.solver_params("f64", tol=1e-2), batch=W["batch"]),
+                          lt, want_raw=True)
+    out = {"sources": {"hp": n_hp, "lp": n_hp + n_lp}, "reference": "GPU FP64 path (HP 1e-10, LP 1e-2)"}
+    for half in ("f16", "bf16"):
+        r = tm.tm_loops_tsm(ctx, g, tm.tsm_params(W["kappa"], W["a"], W["noise_seed"], n_hp, n_lp,
+                                                  hp=tm.solver_params("mixed", tol=1e-10),
+                                                  lp=tm.solver_params("lp", tol=1e-2, half=half),
+                                                  batch=W["batch"]), lt, want_raw=True)
+        if half == "f16":
+            out["hp_mixed_vs_f64"] = op_errors(tm, np, r["raw_hp"], ref["raw_hp"])
+        out[f"lp_{half}_vs_f64_lp"] = op_errors(tm, np, r["raw_lp"], ref["raw_lp"])
+        d = np.abs(r["est"] - ref["est"]) / np.maximum(np.abs(ref["est"]), 1e-300)
+        out[f"tsm_est_{half}_rel_median"] = float(np.median(d))
+    return out
+
+
+def r_hp_lp(tm, ctx, g, W, n=12):
+    """R_HP/LP: GPU time of n HP sources (solve + contraction) over that of n LP
+    sources, from one run with n LP-only sources and one with n HP sources (each
+    with its LP partner, as the method requires)."""
+    lt = W["dims"][3]
+    hp = tm.solver_params("mixed", tol=1e-10)
+    lp = tm.solver_params("lp", tol=1e-2, half=W["half"])
+    t = []
+    for nh, nl in ((0, n), (n, 0)):
+        P = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"] + 7, nh, nl, hp=hp, lp=lp, batch=W["batch"])
+        t0 = time.perf_counter()
+        tm.tm_loops_tsm(ctx, g, P, lt)
+        t.append(time.perf_counter() - t0)
+    return {"value": round((t[1] - t[0]) / t[0], 2), "t_lp_s": round(t[0], 3), "t_hp_plus_lp_s": round(t[1], 3),
+            "sources": n}
+
+
+def serving_segment(tm, np, inputs, ctx, g_big, W, rate_big, n_req, budget_gb=32, load=0.8, seed=5):
+    """Continuous-batching serving run: Poisson arrivals of loop requests on
+    four lattice sizes (the bench's 32^3x64 field and seeded fields of the
+    smaller sizes), 2 kappa mu in {0.0033, 0.01}, N_HP ~ U{4..24},
+    N_LP ~ U{50..500}; the arrival rate is `load` times the capacity estimated
+    from the 32^3x64 throughput scaled by volume.  Latency = arrival (submit)
+    to result on the server clock."""
+    rng = np.random.default_rng(seed)
+    sizes = [(8, 8, 8, 16), (16, 16, 16, 32), (24, 24, 24, 48), tuple(W["dims"])]
+    pools = {}
+    for d in sizes[:3]:
+        pools[d] = [tm.tm_load_gauge(ctx, d, inputs.gauge_field(d, 40 + k), -1, ("f32", "f16", "bf16"))
+                    for k in range(2 if d[0] < 24 else 1)]
+    pools[sizes[3]] = [g_big]
+    vbig = float(np.prod(sizes[3]))
+    reqs = []
+    for i in range(n_req):
+        d = sizes[rng.integers(0, 4)]
+        gp = pools[d][rng.integers(0, len(pools[d]))]
+        a = float(rng.choice([0.0033, 0.01]))
+        nh, nl = int(rng.integers(4, 25)), int(rng.integers(50, 501))
+        P = tm.tsm_params(W["kappa"], a, 1000 + i, nh, nl, hp=tm.solver_params("mixed", tol=1e-10),
+                          lp=tm.solver_params("lp", tol=1e-2, half=W["half"]), batch=W["batch"])
+        service = (nh + nl) * float(np.prod(d)) / vbig / rate_big
+        reqs.append((d, gp, P, nh + nl, service))
+    mean_service = float(np.mean([r[4] for r in reqs]))
+    lam = load / mean_service
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
+    srv = tm.tm_serve_create(ctx, slots=W["batch"], workspace_budget=int(budget_gb) << 30)
+    res = {}
+    try:
+        t0 = time.perf_counter()
+        k = 0
+        while len(res) < n_req:
+            now = time.perf_counter() - t0
+            while k < n_req and arrivals[k] <= now:
+                rc = tm.tm_serve_submit(srv, reqs[k][1], reqs[k][2], k)
+                if rc != 0:
+                    raise RuntimeError(f"serving request {k} rejected ({rc})")
+                k += 1
+            for r in tm.tm_serve_poll(srv):
+                res[r["tag"]] = r
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t0
+        # one request again alone: its result must have the same bits
+        probe = min(range(n_req), key=lambda i: reqs[i][4])
+        tm.tm_serve_submit(srv, reqs[probe][1], reqs[probe][2], 10 ** 6)
+        alone = None
+        while alone is None:
+            for r in tm.tm_serve_poll(srv):
+                alone = r
+            time.sleep(0.001)
+    finally:
+        tm.tm_serve_destroy(srv)
+        for d in sizes[:3]:
+            for gp in pools[d]:
+                tm.tm_free_gauge(ctx, gp)
+    lat = np.array([res[i]["t_done"] - res[i]["t_submit"] for i in range(n_req)])
+    wait = np.array([res[i]["t_admit"] - res[i]["t_submit"] for i in range(n_req)])
+    n_src = sum(r[3] for r in reqs)
+    bad = {}
+    for i in range(n_req):
+        if res[i]["status"] != 0:
+            bad[str(res[i]["status"])] = bad.get(str(res[i]["status"]), 0) + 1
+    ok = not bad
+    same = bool(np.array_equal(alone["est"], res[probe]["est"]) and
+                np.array_equal(alone["var_re"], res[probe]["var_re"]))
+    return {
+        "requests": n_req, "sources": int(n_src), "all_ok": ok, "failed_by_status": bad,
+        "arrivals": f"Poisson at {load:.0%} of the volume-scaled capacity ({lam:.2f} requests/s)",
+        "lattices": ["x".join(map(str, d)) for d in sizes], "slots": W["batch"], "workspace_budget_GB": budget_gb,
+        "latency_p50_s": round(float(np.percentile(lat, 50)), 3), "latency_p99_s": round(float(np.percentile(lat, 99)), 3),
+        "queue_wait_p50_s": round(float(np.percentile(wait, 50)), 3),
+        "sources_per_s": round(n_src / wall, 1), "wall_s": round(wall, 2),
+        "alone_equals_mix": same,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +305,11 @@ def main():
     ap.add_argument("--plain-sources", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests in the serving segment (0 skips it)")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving segment (after one warm-up step)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the precision, R_HP/LP and serving segments")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the copy calibration and the roofline kernel (for counter runs)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -216,6 +353,11 @@ def main():
     for i in range(args.warmup):
         r = tm.tm_loops_tsm(ctx, g, P, lt)
         log(f"warmup step {i} {r['stats']['seconds']:.2f}s")
+    if args.serving_only:
+        rate = n_src / r["stats"]["seconds"]
+        print(json.dumps({"serving": serving_segment(tm, np, inputs, ctx, g, W, rate, args.serve_requests)}),
+              flush=True)
+        return
     torch.cuda.synchronize()
     ta = time.perf_counter()
     last = None
@@ -259,6 +401,17 @@ def main():
             f"{plain['tsm_effective_speedup_local_median']:.1f}x deriv {plain['tsm_effective_speedup_deriv_median']:.1f}x")
 
     roofline = measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)
+
+    precision = rhl = serving = None
+    if not args.no_extra:
+        t0 = time.perf_counter()
+        precision = precision_segment(tm, np, ctx, g, W)
+        rhl = r_hp_lp(tm, ctx, g, W)
+        log(f"precision and R_HP/LP segments in {time.perf_counter() - t0:.1f}s; R_HP/LP {rhl['value']}")
+        if args.serve_requests > 0:
+            serving = serving_segment(tm, np, inputs, ctx, g, W, value, args.serve_requests)
+            log(f"serving: {serving['requests']} requests, p50 {serving['latency_p50_s']}s, "
+                f"p99 {serving['latency_p99_s']}s, {serving['sources_per_s']} sources/s")
 
     # ---- CPU oracle on a bounded sample (one LP source at the same lattice) ----
     cpu = None
@@ -314,6 +467,9 @@ def main():
                   "lp_mean": st["lp_iters"] / max(1, st["lp_solves"]),
                   "reliable_updates": st["reliable_updates"]},
         "plain_f64": plain,
+        "precision": precision,
+        "r_hp_lp": rhl,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

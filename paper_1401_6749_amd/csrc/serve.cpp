@@ -263,6 +263,15 @@ static void worker_main(tm_server *S)
                 S->queue.pop_front();
                 lk.unlock();
                 int rc = admit(S, R);
+                if (rc == TM_ERR_NOMEM) {
+                    // the free bytes suffice but not in one piece: free the
+                    // workspaces of idle batches and try again
+                    for (auto it = S->batches.begin(); it != S->batches.end();) {
+                        BatchRec *br = (it++)->second;
+                        if (batch_idle(br)) drop_batch(S, br);
+                    }
+                    rc = admit(S, R);
+                }
                 lk.lock();
                 if (rc == TM_ERR_NOMEM && !S->active.empty()) {
                     S->queue.push_front(R);  // wait for memory
