@@ -624,7 +624,7 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
 // Timeslice walk through LDS (FP32 and half storage, one slot per block).
 //
 // A block owns a chunk of one timeslice, cy rows (y) x cz planes (z) of full
-// x rows, one site per thread (at most WSPB), for one right-hand side and
+// x rows, one site per thread (at most walk_max), for one right-hand side and
 // walks tw consecutive timeslices.
 // Every input site the walk touches is read from HBM (or L2) once: at each
 // step the thread loads its own site of timeslice t+1, which is at once its
@@ -639,12 +639,16 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
 // neighbour is that of k_dslash; the backward t neighbour is summed first.
 // ---------------------------------------------------------------------------
 constexpr int WSPB = 256;
-// largest chunk (threads per block) per storage precision: FP64 spinors are
-// 192 B, so its two LDS buffers hold 128 sites
+#ifndef TM_WALK_MAX_HALF
+#define TM_WALK_MAX_HALF 512
+#endif
+// largest chunk (threads per block) per storage precision, so that the two
+// LDS buffers of two blocks fit a CU: FP64 128 sites (48 KB per block), FP32
+// 256 (48 KB), FP16/BF16 512 (52 KB)
 template <int SP>
 constexpr int walk_max()
 {
-    return SP == P64 ? 128 : WSPB;
+    return SP == P64 ? 128 : SP == P32 ? WSPB : TM_WALK_MAX_HALF;
 }
 
 template <int SP>
@@ -679,8 +683,8 @@ struct WalkBuf<P32> {
 };
 template <int SP>
 struct WalkBufHalf {
-    u32x4 q[2][3][WSPB];
-    float sc[2][WSPB];
+    u32x4 q[2][3][walk_max<SP>()];
+    float sc[2][walk_max<SP>()];
     __device__ __forceinline__ void get(int b, int d, RawHalf<SP, float> &r) const
     {
 #pragma unroll
@@ -871,7 +875,7 @@ inline int lanes_per_site(int nslot)
 }
 
 // Chunk shape of the walk: cy rows x cz planes of full x rows with cy | Ly,
-// cz | Lz, a multiple of 64 sites up to WSPB, each 64 threads one aligned
+// cz | Lz, a multiple of 64 sites up to maxcs, each 64 threads one aligned
 // 64-site tile (cy = Ly, or cy * Lx/2 a multiple of 64); the fewest halo
 // neighbours per site (2/cy + 2/cz, no term for a dimension the chunk spans),
 // then the largest chunk.  False if no shape fits.
