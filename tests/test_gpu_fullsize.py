@@ -1,0 +1,110 @@
+"""Parity at the benchmark's full size, 32^3 x 64 with its gauge seed, in the
+launch configuration bench.py times: 12 right-hand sides per launch laid out
+with the solver's slot pitch (the timeslice-walk kernels), the FP64 hopping
+term, Z4 codes, and loop sources in matched-iteration mode.  The oracle
+computes whole fields (its Dslash) or a few sampled sources (its solves)."""
+import numpy as np
+import pytest
+
+from paper_1401_6749_amd import inputs
+from tests import gpu_util as GU
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (32, 32, 32, 64)
+KAPPA, A = 0.1636, 0.0033
+
+
+def slot_pitch(nbytes):
+    return (nbytes + 255) // 256 * 256 + 17 * 256
+
+
+@pytest.fixture(scope="module")
+def big():
+    from paper_1401_6749_amd import tm
+
+    U = inputs.gauge_field(DIMS, 4)
+    g = GU.load(DIMS, U)
+    yield U, g
+    tm.tm_free_gauge(GU.context(), g)
+
+
+def _hop_12(g, prec, psis):
+    """tm_dslash_ex hop on 12 right-hand sides at the solver's slot pitch;
+    psis: two canonical spinors used alternately."""
+    torch = GU.torch_mod()
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    nrhs = 12
+    fb = tm.tm_field_bytes(g, prec, True)
+    pitch = slot_pitch(fb)
+    fin = torch.zeros(nrhs * pitch, dtype=torch.uint8, device="cuda")
+    dev = [GU.to_dev(p[None]) for p in psis]
+    for r in range(nrhs):
+        tm.tm_field_import(ctx, g, prec, 1, dev[r % 2], fin[r * pitch:r * pitch + fb])
+    fout = torch.zeros_like(fin)
+    tm.tm_dslash_ex(ctx, g, "hop", KAPPA, A, prec, nrhs, fin, pitch, fout, pitch)
+    V = int(np.prod(DIMS))
+    canon = torch.zeros(1, V, 4, 3, 2, dtype=torch.float64, device="cuda")
+
+    def export(r):
+        tm.tm_field_export(ctx, g, prec, 1, fout[r * pitch:r * pitch + fb], canon)
+        torch.cuda.synchronize()
+        return GU.from_dev(canon).reshape(V, 4, 3)
+
+    return export
+
+
+def test_fullsize_hop_12rhs(oracle, big):
+    """FP64, FP32 and FP16 hop at 32^3x64, 12 RHS per launch: every RHS against
+    the oracle's FP64 hop of the same input (FP64 <= 1e-14; FP32 / FP16 within
+    their storage rounding, as on the small lattices)."""
+    U, g = big
+    psis = [inputs.random_spinor(DIMS, 21), inputs.random_spinor(DIMS, 22)]
+    want = [oracle.dhop(DIMS, -1, U, p) for p in psis]
+    for prec, tol, rhs in (("f64", 1e-14, (0, 1, 11)), ("f32", 2e-6, (0, 11)), ("f16", 3e-3, range(12))):
+        export = _hop_12(g, prec, psis)
+        first = {}
+        for r in rhs:
+            got = export(r)
+            assert GU.relerr(got, want[r % 2]) < tol, (prec, r)
+            # no right-hand side sees another's data: equal inputs give equal bits
+            if r % 2 in first:
+                assert np.array_equal(got, first[r % 2]), (prec, r)
+            else:
+                first[r % 2] = got
+
+
+def test_fullsize_z4_codes(oracle):
+    torch = GU.torch_mod()
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    V = int(np.prod(DIMS))
+    for seed, src in [(104, 0), (104, 1047)]:
+        out = torch.empty(V, 4, 3, 2, dtype=torch.float64, device="cuda")
+        tm.tm_z4_source(ctx, DIMS, seed, src, out)
+        torch.cuda.synchronize()
+        got = GU.from_dev(out).reshape(V, 4, 3)
+        assert np.array_equal(got.view(np.float64), oracle.z4_source(DIMS, seed, src).view(np.float64))
+
+
+def test_fullsize_loops_matched_iterations(oracle, big):
+    """Loop spin matrices of sampled sources at 32^3x64, five CG iterations
+    each: the FP64 path to 1e-10 of the oracle; the FP16 LP path (12 sources
+    in one batch, the bench's launch shape) within its storage rounding."""
+    from paper_1401_6749_amd import tm
+
+    U, g = big
+    ctx = GU.context()
+    lt = DIMS[3]
+    ref = oracle.loops_tsm(DIMS, -1, U, KAPPA, A, 104, 0, 12, lp_fixed_iters=5, source_ids=[0, 11],
+                           return_raw=True)
+    P64 = tm.tsm_params(KAPPA, A, 104, 0, 12, lp=tm.solver_params("f64", fixed_iters=5), batch=12)
+    r64 = tm.tm_loops_tsm(ctx, g, P64, lt, want_raw=True)
+    P16 = tm.tsm_params(KAPPA, A, 104, 0, 12, lp=tm.solver_params("lp", fixed_iters=5, half="f16"), batch=12)
+    r16 = tm.tm_loops_tsm(ctx, g, P16, lt, want_raw=True)
+    for j in (0, 11):
+        assert GU.relerr(r64["raw_lp"][j], ref["lp_raw"][j]) < 1e-10, j
+        assert GU.relerr(r16["raw_lp"][j], ref["lp_raw"][j]) < 5e-3, j
