@@ -18,6 +18,8 @@ in NumPy:
   * ``loops_tsm``               the whole path: Z4 sources (Sec. 2), HP and LP
                                 solves (Sec. 2.1), contractions at all
                                 timeslices (Sec. 2.2), projection and TSM.
+  * ``loops_oet``               the same with the one-end trick estimators
+                                (Sec. 2.2, Eq. loopVv and Eq. loopStD).
 
 Array layouts (complex128): spinor (V, 4, 3), gauge (V, 4, 3, 3), with
 lex = x + Lx*(y + Ly*(z + Lz*t)).  ``a`` always means 2*kappa*mu.
@@ -225,7 +227,10 @@ def z4_source(dims, seed, src):
 # ----------------------------------------------------------------------------
 def contract(dims, tbc, U, eta, s):
     """Spin matrices per timeslice, shape (9, T, 4, 4): kind 0 local,
-    1..4 forward F^nu, 5..8 backward B^nu (nu = x, y, z, t)."""
+    1..4 forward F^nu, 5..8 backward B^nu (nu = x, y, z, t).
+
+    ``eta`` is any left vector: the noise for the standard estimator, the
+    solution itself for the one-end trick (``loops_oet``)."""
     d = _dims(dims)
     v = volume(d)
     U = _c(U, (v, 4, 3, 3))
@@ -243,8 +248,10 @@ N_OPS = N_LOCAL + N_DERIV + N_SYM
 SYM_PAIRS = [(m, n) for m in range(4) for n in range(m, 4)]
 
 
-def project(P):
+def project(P, gam=None):
     """Spin matrices (9, T, 4, 4) -> operator loops (90, T) complex.
+
+    ``gam`` replaces the 16 insertions G (e.g. g5 G for the one-end trick).
 
     ops 0..15         L_G(t)      = sum_ab G_ab P_ab(t)              (local, eta^dag G s)
     ops 16+4g+nu      L^D_{G,nu}  = 1/4 [F(t) + F(t-d) - B(t) - B(t-d)],
@@ -253,7 +260,7 @@ def project(P):
     ops 80..89        O_mn = (L^D_{g_m,n} + L^D_{g_n,m}) / 2 for m <= n.
     """
     P = np.asarray(P)
-    G = gammas16()
+    G = gammas16() if gam is None else np.asarray(gam)
     T = P.shape[1]
     out = np.zeros((N_OPS, T), dtype=np.complex128)
     proj = np.einsum("gab,ktab->gkt", G, P)  # (16, 9, T)
@@ -356,4 +363,64 @@ def loops_tsm(dims, tbc, U, kappa, a, noise_seed, n_hp, n_lp, hp_tol=1e-10, lp_t
         lpb = np.array([lp_loops[j] for j in range(n_hp, n_hp + n_lp)]).reshape(n_lp, N_OPS, T)
         est, vre, vim = tsm_combine(hp, lpc, lpb)
         res.update(est=est, var_re=vre, var_im=vim)
+    return res
+
+
+def oet_gammas():
+    """Insertions of the one-end trick estimators: g5 G (isovector) and
+    g5 G g5 (isoscalar) for the 16 G of ``gammas16``."""
+    G = gammas16()
+    g5 = G[5]
+    return np.einsum("ab,gbc->gac", g5, G), np.einsum("ab,gbc,cd->gad", g5, G, g5)
+
+
+def loops_oet(dims, tbc, U, kappa, a, noise_seed, n_hp, n_lp, hp_tol=1e-10, lp_tol=1e-2,
+              max_iter=100000, lp_fixed_iters=0, source_ids=None, return_raw=False):
+    """The one-end trick (Sec. 2.2) with the truncated solver method.
+
+    For each source s = M_u^-1 eta (M_u = D_W + i a g5, a = 2 kappa mu):
+      isovector  L^vv_X = -2 i a  s^dag g5 X s          (Eq. loopVv)
+                 estimates Tr(M_u^-1 X) - Tr(M_d^-1 X)
+      isoscalar  L^ws_X =  2      s^dag g5 X g5 D_W s   (Eq. loopStD)
+                 estimates Tr(M_u^-1 X) + Tr(M_d^-1 X)
+    with D_W = M at a = 0, for the same 90 operators X as ``loops_tsm`` (the
+    spin matrices are ``contract`` with left vector s and right vector s or
+    D_W s).  The sign of the isovector factor follows from
+    M_u^-1 - M_d^-1 = -2 i a M_u^-1 g5 M_d^-1 and M_d^-1 = g5 (M_u^-1)^dag g5
+    in this normalisation.  Same source sets and TSM combination as
+    ``loops_tsm``; returns est_vv / est_ws, their variances, per-source loops
+    and (optionally) the raw spin matrices raw_vv / raw_ws.
+    """
+    T = int(dims[3])
+    gvv, gws = oet_gammas()
+    ids = list(range(n_hp + n_lp)) if source_ids is None else list(source_ids)
+    loops = {"hp_vv": {}, "hp_ws": {}, "lp_vv": {}, "lp_ws": {}}
+    raws = {"hp_vv": {}, "hp_ws": {}, "lp_vv": {}, "lp_ws": {}}
+
+    def one(tag, j, s):
+        R = apply_M(dims, tbc, U, kappa, 0.0, s)
+        Pvv = -2j * a * contract(dims, tbc, U, s, s)
+        Pws = 2.0 * contract(dims, tbc, U, s, R)
+        raws[tag + "_vv"][j], raws[tag + "_ws"][j] = Pvv, Pws
+        loops[tag + "_vv"][j] = project(Pvv, gvv)
+        loops[tag + "_ws"][j] = project(Pws, gws)
+
+    t0 = time.perf_counter()
+    for j in ids:
+        eta = z4_source(dims, noise_seed, j)
+        if j < n_hp:
+            s, _, _, _ = solve(dims, tbc, U, kappa, a, eta, tol=hp_tol, max_iter=max_iter)
+            one("hp", j, s)
+        s, _, _, _ = solve(dims, tbc, U, kappa, a, eta, tol=lp_tol, max_iter=max_iter, fixed_iters=lp_fixed_iters)
+        one("lp", j, s)
+    res = {"seconds": time.perf_counter() - t0, "loops": loops}
+    if return_raw:
+        res["raw"] = raws
+    if source_ids is None:
+        for f in ("vv", "ws"):
+            hp = np.array([loops["hp_" + f][j] for j in range(n_hp)]).reshape(n_hp, N_OPS, T)
+            lpc = np.array([loops["lp_" + f][j] for j in range(n_hp)]).reshape(n_hp, N_OPS, T)
+            lpb = np.array([loops["lp_" + f][j] for j in range(n_hp, n_hp + n_lp)]).reshape(n_lp, N_OPS, T)
+            est, vre, vim = tsm_combine(hp, lpc, lpb)
+            res.update({"est_" + f: est, "var_re_" + f: vre, "var_im_" + f: vim})
     return res
