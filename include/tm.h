@@ -264,6 +264,24 @@ typedef struct tm_tsm_stats {
 int tm_loops_tsm(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *params, double *est,
                  double *var_re, double *var_im, double *raw, tm_tsm_stats *stats);
 
+/* The same sources, solves and TSM combination with the one-end trick
+ * estimators of the twisted-mass formulation (Sec. 2.2, Eq. loopVv and
+ * Eq. loopStD), for the same 90 operators X.  With s = M_u^-1 eta
+ * (M_u = D_W + i a g5 the operator of this library, M_d the same with -a,
+ * D_W = M at a = 0):
+ *   flavour 0 (isovector)  -2 i a s^dag g5 X s       -> Tr(M_u^-1 X) - Tr(M_d^-1 X)
+ *   flavour 1 (isoscalar)   2 s^dag g5 X g5 D_W s    -> Tr(M_u^-1 X) + Tr(M_d^-1 X)
+ * (the isovector sign follows from M_u^-1 - M_d^-1 = -2ia M_u^-1 g5 M_d^-1
+ * in this normalisation).  Outputs as tm_loops_tsm with a leading flavour
+ * index: est [2][TM_N_OPS][Lt][2], var_re/var_im [2][TM_N_OPS][Lt], raw
+ * (optional) [2][n_hp + n_hp + n_lp][9][Lt][4][4][2] holding the spin
+ * matrices with the factor (-2ia or 2) applied, to be projected with the
+ * insertions g5 G (flavour 0) and g5 G g5 (flavour 1).  Each source costs
+ * one more Dslash application (D_W s) and one more contraction than
+ * tm_loops_tsm.  Errors as tm_loops_tsm. */
+int tm_loops_oet(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *params, double *est,
+                 double *var_re, double *var_im, double *raw, tm_tsm_stats *stats);
+
 /* Project spin matrices [n][9][Lt][4][4][2] (host) onto the 90 operator
  * loops [n][TM_N_OPS][Lt][2] (host), as in tm_loops_tsm. */
 int tm_project_loops(int n, int lt, const double *raw, double *ops);

@@ -622,13 +622,34 @@ extern "C" int tm_project_loops(int n, int lt, const double *raw, double *ops)
 // loops with the truncated solver method
 // ---------------------------------------------------------------------------
 int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *vre, double *vim,
-            double *raw_host, tm_tsm_stats *stats);
+            double *raw_host, tm_tsm_stats *stats, bool oet = false);
 
 extern "C" int tm_loops_tsm(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *var_re,
                             double *var_im, double *raw, tm_tsm_stats *stats)
 {
     if (!ctx) return TM_ERR_ARG;
     return tsm_run(ctx, G, P, est, var_re, var_im, raw, stats);
+}
+
+extern "C" int tm_loops_oet(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *var_re,
+                            double *var_im, double *raw, tm_tsm_stats *stats)
+{
+    if (!ctx) return TM_ERR_ARG;
+    return tsm_run(ctx, G, P, est, var_re, var_im, raw, stats, true);
+}
+
+// insertion tables of the one-end trick: g5 G (flavour 0) and g5 G g5 (flavour 1),
+// from the table of G (entry = column | phase << 2, phase 0..3 = 1, i, -1, -i)
+static void oet_gamma_tables(int vv[64], int ws[64])
+{
+    const int *g = gamma_table();
+    for (int gi = 0; gi < 16; gi++)
+        for (int a = 0; a < 4; a++) {
+            const int e = g[4 * gi + a], col = e & 3, ph = e >> 2;
+            const int fa = a >= 2 ? 2 : 0, fc = col >= 2 ? 2 : 0;
+            vv[4 * gi + a] = col | (((ph + fa) & 3) << 2);
+            ws[4 * gi + a] = col | (((ph + fa + fc) & 3) << 2);
+        }
 }
 
 int tsm_check(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P)
@@ -646,9 +667,9 @@ int tsm_check(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P)
 }
 
 int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *vre, double *vim,
-            double *raw_host, tm_tsm_stats *stats)
+            double *raw_host, tm_tsm_stats *stats, bool oet)
 {
-    if (!est || !vre || !vim) return set_err(ctx, TM_ERR_ARG, "tm_loops_tsm: null output");
+    if (!est || !vre || !vim) return set_err(ctx, TM_ERR_ARG, "tm_loops: null output");
     int rc = tsm_check(ctx, G, P);
     if (rc) return rc;
     const int batch = P->batch > 0 ? std::min(P->batch, MAX_SLOTS) : 12;
@@ -656,14 +677,21 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
     const double t0 = now_s();
     const int lt = G->dims[3];
     const int n_hp = P->n_hp, n_lpt = P->n_hp + P->n_lp;
+    const int nf = oet ? 2 : 1;  // estimators: eta^dag G s, or the isovector and isoscalar one-end trick
     const size_t raw_per = (size_t)9 * lt * 32;  // doubles per source
     const size_t ops_per = (size_t)TM_N_OPS * lt * 2;
-    const size_t dev_doubles = (size_t)(n_hp + n_lpt) * (raw_per + ops_per) + ops_per * 2;
+    const size_t src_raw = (size_t)(n_hp + n_lpt) * raw_per, src_ops = (size_t)(n_hp + n_lpt) * ops_per;
+    const size_t dev_doubles = nf * (src_raw + src_ops + ops_per * 2);
     double *dbuf = (double *)dalloc(ctx, dev_doubles * sizeof(double));
-    if (!dbuf) return set_err(ctx, TM_ERR_NOMEM, "tm_loops_tsm: no memory for per-source loops");
-    double *raw_hp = dbuf, *raw_lp = raw_hp + n_hp * raw_per;
-    double *ops_hp = raw_lp + n_lpt * raw_per, *ops_lp = ops_hp + n_hp * ops_per;
-    double *d_est = ops_lp + n_lpt * ops_per, *d_vre = d_est + ops_per, *d_vim = d_vre + ops_per / 2;
+    if (!dbuf) return set_err(ctx, TM_ERR_NOMEM, "tm_loops: no memory for per-source loops");
+    // flavour f: raw [n_hp | n_lpt] sources, ops likewise, then est and variances
+    auto raw_hp = [&](int f) { return dbuf + f * src_raw; };
+    auto raw_lp = [&](int f) { return raw_hp(f) + n_hp * raw_per; };
+    double *opsb = dbuf + nf * src_raw;
+    auto ops_hp = [&](int f) { return opsb + f * src_ops; };
+    auto ops_lp = [&](int f) { return ops_hp(f) + n_hp * ops_per; };
+    double *estb = opsb + nf * src_ops;
+    auto d_est = [&](int f) { return estb + f * 2 * ops_per; };
     std::vector<Job> hp(n_hp), lp(n_lpt);
     std::vector<Job *> qh, ql;
     for (int i = 0; i < n_hp; i++) {
@@ -672,7 +700,9 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         j.seed = P->noise_seed;
         j.src = i;
         job_from(j, P->hp, P->kappa, P->two_kappa_mu);
-        j.raw_out = raw_hp + i * raw_per;
+        j.raw_out = raw_hp(0) + i * raw_per;
+        j.oet = oet;
+        j.raw_out2 = oet ? raw_hp(1) + i * raw_per : nullptr;
         j.want_true = P->want_true_resid;
         j.hp = true;
         qh.push_back(&j);
@@ -683,7 +713,9 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         j.seed = P->noise_seed;
         j.src = i;
         job_from(j, P->lp, P->kappa, P->two_kappa_mu);
-        j.raw_out = raw_lp + i * raw_per;
+        j.raw_out = raw_lp(0) + i * raw_per;
+        j.oet = oet;
+        j.raw_out2 = oet ? raw_lp(1) + i * raw_per : nullptr;
         j.want_true = P->want_true_resid;
         ql.push_back(&j);
     }
@@ -713,21 +745,27 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
     hipStream_t s = streams.empty() ? nullptr : streams.back();
     if (!rc) {
         for (hipStream_t x : streams) hipStreamSynchronize(x);
-        const int *gt = gamma_table();
-        launch_project(n_hp, lt, raw_hp, ops_hp, gt, s);
-        launch_project(n_lpt, lt, raw_lp, ops_lp, gt, s);
-        launch_tsm_combine(n_hp, P->n_lp, lt, ops_hp, ops_lp, ops_lp + (size_t)n_hp * ops_per, d_est, d_vre, d_vim, s);
-        hipError_t e = hipMemcpyAsync(est, d_est, ops_per * sizeof(double), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(vre, d_vre, ops_per / 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(vim, d_vim, ops_per / 2 * sizeof(double), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess && raw_host) {
-            e = hipMemcpyAsync(raw_host, raw_hp, (size_t)n_hp * raw_per * sizeof(double), hipMemcpyDeviceToHost, s);
+        int tv[64], tw[64];
+        if (oet) oet_gamma_tables(tv, tw);
+        hipError_t e = hipSuccess;
+        for (int f = 0; f < nf && e == hipSuccess; f++) {
+            const int *gt = !oet ? gamma_table() : f == 0 ? tv : tw;
+            double *de = d_est(f), *dvre = de + ops_per, *dvim = dvre + ops_per / 2;
+            launch_project(n_hp, lt, raw_hp(f), ops_hp(f), gt, s);
+            launch_project(n_lpt, lt, raw_lp(f), ops_lp(f), gt, s);
+            launch_tsm_combine(n_hp, P->n_lp, lt, ops_hp(f), ops_lp(f), ops_lp(f) + (size_t)n_hp * ops_per, de, dvre,
+                               dvim, s);
+            e = hipMemcpyAsync(est + f * ops_per, de, ops_per * sizeof(double), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess)
-                e = hipMemcpyAsync(raw_host + n_hp * raw_per, raw_lp, (size_t)n_lpt * raw_per * sizeof(double),
-                                   hipMemcpyDeviceToHost, s);
+                e = hipMemcpyAsync(vre + f * ops_per / 2, dvre, ops_per / 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(vim + f * ops_per / 2, dvim, ops_per / 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess && raw_host)
+                e = hipMemcpyAsync(raw_host + f * src_raw, raw_hp(f), src_raw * sizeof(double), hipMemcpyDeviceToHost,
+                                   s);
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) rc = set_err(ctx, TM_ERR_HIP, "tm_loops_tsm: %s", hipGetErrorString(e));
+        if (e != hipSuccess) rc = set_err(ctx, TM_ERR_HIP, "tm_loops: %s", hipGetErrorString(e));
     }
     for (hipStream_t x : streams) {
         (void)hipStreamSynchronize(x);
@@ -762,8 +800,8 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         stats->lp_seconds = lp_end > 0 ? lp_end - t0 : 0;
     }
     if (rc) return rc;
-    if (worst == TM_ERR_NUMERIC) return set_err(ctx, worst, "tm_loops_tsm: non-finite values in a solve");
-    if (worst == TM_ERR_NOCONV) return set_err(ctx, worst, "tm_loops_tsm: a solve reached max_iter");
+    if (worst == TM_ERR_NUMERIC) return set_err(ctx, worst, "tm_loops: non-finite values in a solve");
+    if (worst == TM_ERR_NOCONV) return set_err(ctx, worst, "tm_loops: a solve reached max_iter");
     return TM_OK;
 }
 

@@ -75,7 +75,7 @@ size_t batch_footprint(const tm_gauge *G, Kind kind, int S)
     b += (size_t)S * 2 * slot_pitch(half_bytes(xr, g));  // x, r
     if (kind == K_MIXED) b += (size_t)S * 2 * half_bytes(P64, g);  // x64, b64
     b += (size_t)S * 2 * g.vh * sizeof(uint32_t);      // noise codes
-    b += 3 * (scratch_bytes(g, kind, S) + 256);         // scratch FA, FB, FC
+    b += (lp_kind(kind) ? 4 : 3) * (scratch_bytes(g, kind, S) + 256);  // scratch FA, FB, FC (, FD)
     b += (size_t)S * ntile_of(g) * sizeof(double) + 4096;
     b += (size_t)(lp_kind(kind) ? S : 1) * contract_part_doubles(g) * sizeof(double) + 256;
     b += (size_t)S * sizeof(SlotState) + 64 * sizeof(double) + 16 * 256;
@@ -146,6 +146,7 @@ int batch_create(tm_context *ctx, const tm_gauge *G, Kind kind, int S, int chunk
     b->FA = carve(cur, sb);
     b->FB = carve(cur, sb);
     b->FC = carve(cur, sb);
+    if (lp_kind(kind)) b->FD = carve(cur, sb);
     b->partial = (double *)carve(cur, (size_t)S * b->nblk * sizeof(double) + 4096);
     b->cpart = (double *)carve(cur, (size_t)(lp_kind(kind) ? S : 1) * contract_part_doubles(g) * sizeof(double));
     b->dres = (double *)carve(cur, 64 * sizeof(double));
@@ -581,8 +582,22 @@ static void harvest_lp_run(Batch *b, int s0, int n)
     char *se32 = b->FB, *so32 = b->FC;
     launch_convert(b->xr, P32, g, b->x + s0 * b->hxr, b->hxr, se32, w, n, s);
     dsl_codes_run(b, P32, 2, CM_RECON, 1, s0, n, se32, w, so32, w, j->kappa, j->a);
-    RawOuts R{};
-    for (int i = 0; i < n; i++) R.p[i] = b->slot_job[s0 + i]->raw_out;
+    RawOuts R{}, R2{};
+    for (int i = 0; i < n; i++) {
+        R.p[i] = b->slot_job[s0 + i]->raw_out;
+        R2.p[i] = b->slot_job[s0 + i]->raw_out2;
+    }
+    if (j->oet) {
+        // one-end trick: isovector -2ia s^dag g5 X s, isoscalar 2 s^dag g5 X g5 D_W s with
+        // D_W s = (s_e - kappa D_eo s_o, s_o - kappa D_oe s_e)
+        char *re = b->FA, *ro = b->FD;
+        dsl_run(b, P32, false, EPI_PLAIN, CM_M, 0, so32, w, se32, w, re, w, j->kappa, 0.0, n);
+        dsl_run(b, P32, false, EPI_PLAIN, CM_M, 1, se32, w, so32, w, ro, w, j->kappa, 0.0, n);
+        launch_contract_lr(P32, g, b->G->links[P32], se32, so32, w, se32, so32, w, b->cpart, R, n, 0.0, -2.0 * j->a,
+                           s);
+        launch_contract_lr(P32, g, b->G->links[P32], re, ro, w, se32, so32, w, b->cpart, R2, n, 2.0, 0.0, s);
+        return;
+    }
     launch_contract(P32, g, b->G->links[P32], se32, so32, w, b->codes + (size_t)s0 * 2 * g.vh, b->cpart, R, n, s);
 }
 
@@ -639,9 +654,20 @@ static void harvest64(Batch *b, int slot, const SlotState &S, Job *j)
     if (j->noise) {
         // s_o = A^-1 (eta_o + kappa D_oe s_e) with eta_o from the codes
         dsl_codes(b, P64, 2, CM_RECON, 1, slot, se, so, j->kappa, j->a);
-        if (j->raw_out)
+        if (j->raw_out && j->oet) {
+            // one-end trick (see harvest_lp_run), D_W s in FA = [even | odd]
+            char *re = b->FA, *ro = b->FA + b->h64;
+            d64(b, false, EPI_PLAIN, CM_M, 0, so, se, re, j->kappa, 0.0);
+            d64(b, false, EPI_PLAIN, CM_M, 1, se, so, ro, j->kappa, 0.0);
+            RawOuts R{}, R2{};
+            R.p[0] = j->raw_out;
+            R2.p[0] = j->raw_out2;
+            launch_contract_lr(P64, g, b->G->links[P64], se, so, 0, se, so, 0, b->cpart, R, 1, 0.0, -2.0 * j->a, s);
+            launch_contract_lr(P64, g, b->G->links[P64], re, ro, 0, se, so, 0, b->cpart, R2, 1, 2.0, 0.0, s);
+        } else if (j->raw_out) {
             launch_contract(P64, g, b->G->links[P64], se, so, b->codes + (size_t)slot * 2 * g.vh, b->cpart,
                             j->raw_out, s);
+        }
     } else {
         load_eta(b, slot, j);
         d64(b, false, EPI_PLAIN, CM_RECON, 1, se, Eo, so, j->kappa, j->a);
@@ -712,7 +738,7 @@ int batch_process(Batch *b, std::vector<Job *> &finished)
         if (lp_harvest(b, j)) {
             static const int cap = run_cap("TM_HARVEST_RUN");
             while (s + n < S && n < std::min(b->wslots, cap) && done(s + n) && lp_harvest(b, b->slot_job[s + n]) &&
-                   same_params(b->slot_job[s + n], j))
+                   same_params(b->slot_job[s + n], j) && b->slot_job[s + n]->oet == j->oet)
                 n++;
             harvest_lp_run(b, s, n);
         } else if (prep_prec(b, j) != P32) {

@@ -88,11 +88,13 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 // Contractions.  A block owns a chunk of CPB sites of one timeslice (both
 // parities); each thread accumulates its sites, the block reduces in a fixed
 // order and writes one partial per (timeslice, chunk); a second kernel sums
-// the chunks of each timeslice in order.  Accumulators hold unscaled noise
-// (+-1 +- i); the factor 2^-1/2 is applied once at the end.
-//   kind 0:      P_ab  = sum conj(eta_a) . s_b
-//   kind 1+nu:   F_ab  = sum conj(eta_a(x)) . [U_nu(x) s(x+nu)]_b
-//   kind 5+nu:   B_ab  = sum conj([U_nu(x) eta(x+nu)]_a) . s_b(x)
+// the chunks of each timeslice in order and applies one complex factor.
+//   kind 0:      P_ab  = sum conj(l_a) . s_b
+//   kind 1+nu:   F_ab  = sum conj(l_a(x)) . [U_nu(x) s(x+nu)]_b
+//   kind 5+nu:   B_ab  = sum conj([U_nu(x) l(x+nu)]_a) . s_b(x)
+// The left vector l is the noise from its Z4 codes (unscaled +-1 +- i; factor
+// 2^-1/2), or, for the one-end trick, a field: the solution itself (factor
+// -2ia, isovector) with s the solution or D_W applied to it (factor 2).
 // ---------------------------------------------------------------------------
 constexpr int CT = 128;        // threads per contraction block
 constexpr int SPT = 8;         // sites per thread (amortises the block reductions)
@@ -132,9 +134,27 @@ __device__ __forceinline__ bool contract_site(const Geom &g, int t, int q, int &
 //   KIND 0: local; KIND 1+nu: F^nu; KIND 5+nu: B^nu.
 // Products in the precision of s (FP64 for HP and FP64 solves, FP32 for LP
 // solves, with links of the same precision); sums always in FP64.
-template <int KIND, int SPS>
+// left vector: Z4 codes (unscaled noise) or a field of precision SPS
+template <int SPS, bool FIELD>
+struct LeftVec {
+    const uint32_t *codes;
+    const char *fld[2];
+    template <class T>
+    __device__ __forceinline__ void get(const Geom &g, int par, int cb, cpx<T> l[12]) const
+    {
+        if constexpr (FIELD) {
+            SpinorIO<SPS>::load(fld[par], g.vh, cb, l);
+        } else {
+            const uint32_t c = codes[(size_t)par * g.vh + cb];
+#pragma unroll
+            for (int k = 0; k < 12; k++) l[k] = z4_unscaled<T>(c, k);
+        }
+    }
+};
+
+template <int KIND, int SPS, bool FIELD>
 __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, const char *s_fld[2],
-                                              const uint32_t *codes, int t, int chunk, double (&acc)[32])
+                                              const LeftVec<SPS, FIELD> &left, int t, int chunk, double (&acc)[32])
 {
     using T = typename Real<SPS>::T;
 #pragma unroll
@@ -143,17 +163,16 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
     for (int k = 0; k < SPT; k++) {
         int par, cb;
         if (!contract_site(g, t, chunk * CPB + k * CT + threadIdx.x, par, cb)) continue;
-        const uint32_t ce = codes[(size_t)par * g.vh + cb];
         if constexpr (KIND == 0) {
-            cpx<T> sv[12];
+            cpx<T> lv[12], sv[12];
+            left.get(g, par, cb, lv);
             SpinorIO<SPS>::load(s_fld[par], g.vh, cb, sv);
 #pragma unroll
             for (int a = 0; a < 4; a++)
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
-                    cpx<T> f = cmulc(z4_unscaled<T>(ce, 3 * a), sv[3 * b]) +
-                                    cmulc(z4_unscaled<T>(ce, 3 * a + 1), sv[3 * b + 1]) +
-                                    cmulc(z4_unscaled<T>(ce, 3 * a + 2), sv[3 * b + 2]);
+                    cpx<T> f = cmulc(lv[3 * a], sv[3 * b]) + cmulc(lv[3 * a + 1], sv[3 * b + 1]) +
+                               cmulc(lv[3 * a + 2], sv[3 * b + 2]);
                     acc[2 * (4 * a + b)] += (double)f.re;
                     acc[2 * (4 * a + b) + 1] += (double)f.im;
                 }
@@ -165,8 +184,9 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
             LinkIO<SPS>::load(G, g.vh, par, NU, cb, L);
             const T sg = (NU == 3 && g.tbc < 0 && s.t == g.L[3] - 1) ? (T)-1 : (T)1;
             if constexpr (KIND <= 4) {
-                // F: conj(eta_a(x)) . (U s(x+nu))_b
-                cpx<T> snb[12];
+                // F: conj(l_a(x)) . (U s(x+nu))_b
+                cpx<T> lv[12], snb[12];
+                left.get(g, par, cb, lv);
                 SpinorIO<SPS>::load(s_fld[1 - par], g.vh, nf, snb);
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
@@ -176,25 +196,22 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
                     umul(L, h, w);
 #pragma unroll
                     for (int a = 0; a < 4; a++) {
-                        cpx<T> f = cmulc(z4_unscaled<T>(ce, 3 * a), w[0]) +
-                                        cmulc(z4_unscaled<T>(ce, 3 * a + 1), w[1]) +
-                                        cmulc(z4_unscaled<T>(ce, 3 * a + 2), w[2]);
+                        cpx<T> f = cmulc(lv[3 * a], w[0]) + cmulc(lv[3 * a + 1], w[1]) + cmulc(lv[3 * a + 2], w[2]);
                         acc[2 * (4 * a + b)] += (double)f.re;
                         acc[2 * (4 * a + b) + 1] += (double)f.im;
                     }
                 }
             } else {
-                // B: conj((U eta(x+nu))_a) . s_b(x)
-                const uint32_t cf = codes[(size_t)(1 - par) * g.vh + nf];
-                cpx<T> sv[12];
+                // B: conj((U l(x+nu))_a) . s_b(x)
+                cpx<T> lf[12], sv[12];
+                left.get(g, 1 - par, nf, lf);
                 SpinorIO<SPS>::load(s_fld[par], g.vh, cb, sv);
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
                     cpx<T> e[3], v[3];
 #pragma unroll
                     for (int c = 0; c < 3; c++) {
-                        const cpx<T> z = z4_unscaled<T>(cf, 3 * a + c);
-                        e[c] = cpx<T>{sg * z.re, sg * z.im};
+                        e[c] = cpx<T>{sg * lf[3 * a + c].re, sg * lf[3 * a + c].im};
                     }
                     umul(L, e, v);
 #pragma unroll
@@ -210,21 +227,26 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
 }
 
 // partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
-// blockIdx.y = source
-template <int SPS>
+// blockIdx.y = source; the left vector is the source's codes (FIELD false) or
+// the field pair (l_even, l_odd) + i * l_stride
+template <int SPS, bool FIELD>
 __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd,
-                                                 size_t s_stride, const uint32_t *codes, double *cpart, int nchunk,
+                                                 size_t s_stride, const char *l_even, const char *l_odd,
+                                                 size_t l_stride, const uint32_t *codes, double *cpart, int nchunk,
                                                  size_t part_stride)
 {
     __shared__ double lds[(CT / 64) * 32];
     const int t = blockIdx.x / nchunk, chunk = blockIdx.x - t * nchunk;
     const int i = blockIdx.y;
     const char *s_fld[2] = {s_even + (size_t)i * s_stride, s_odd + (size_t)i * s_stride};
-    codes += (size_t)i * 2 * g.vh;
+    LeftVec<SPS, FIELD> left;
+    left.codes = FIELD ? nullptr : codes + (size_t)i * 2 * g.vh;
+    left.fld[0] = FIELD ? l_even + (size_t)i * l_stride : nullptr;
+    left.fld[1] = FIELD ? l_odd + (size_t)i * l_stride : nullptr;
     double *dst = cpart + (size_t)i * part_stride + (size_t)blockIdx.x * 288;
     double acc[32];
-#define TMK_KIND(K)                                                  \
-    contract_kind<K, SPS>(g, G, s_fld, codes, t, chunk, acc);        \
+#define TMK_KIND(K)                                                     \
+    contract_kind<K, SPS, FIELD>(g, G, s_fld, left, t, chunk, acc);     \
     block_write<32>(acc, lds, dst + (K) * 32);
     TMK_KIND(0)
     TMK_KIND(1)
@@ -238,37 +260,53 @@ __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const ch
 #undef TMK_KIND
 }
 
-// raw[kind][t][ab][2] = 2^-1/2 * sum_chunk cpart[t][chunk][kind][ab][2]; blockIdx.y = source
-__global__ void k_contract_final(const double *cpart, int nchunk, int lt, RawOuts R, size_t part_stride)
+// raw[kind][t][ab] = (sr + i si) * sum_chunk cpart[t][chunk][kind][ab] (complex); blockIdx.y = source
+__global__ void k_contract_final(const double *cpart, int nchunk, int lt, RawOuts R, size_t part_stride, double sr,
+                                 double si)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over lt * 288
-    if (i >= lt * 288) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over lt * 144 complex entries
+    if (i >= lt * 144) return;
     cpart += (size_t)blockIdx.y * part_stride;
     double *raw = R.p[blockIdx.y];
-    const int t = i / 288, e = i - t * 288;
-    double s = 0.0;
-    for (int c = 0; c < nchunk; c++) s += cpart[((size_t)t * nchunk + c) * 288 + e];
+    const int t = i / 144, e = 2 * (i - t * 144);
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < nchunk; c++) {
+        re += cpart[((size_t)t * nchunk + c) * 288 + e];
+        im += cpart[((size_t)t * nchunk + c) * 288 + e + 1];
+    }
     const int kind = e / 32, ab = e - kind * 32;
-    raw[((size_t)kind * lt + t) * 32 + ab] = s * TM_RSQRT2;
+    raw[((size_t)kind * lt + t) * 32 + ab] = re * sr - im * si;
+    raw[((size_t)kind * lt + t) * 32 + ab + 1] = re * si + im * sr;
 }
 
 size_t contract_part_doubles(const Geom &g) { return (size_t)g.L[3] * contract_nchunk(g) * 288; }
 
-void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
-                     size_t s_stride, const uint32_t *codes, double *cpart, const RawOuts &raw, int n, hipStream_t s)
+template <bool FIELD>
+static void contract_t(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
+                       size_t s_stride, const char *l_even, const char *l_odd, size_t l_stride,
+                       const uint32_t *codes, double *cpart, const RawOuts &raw, int n, double sr, double si,
+                       hipStream_t s)
 {
     if (n < 1) return;
     const int nchunk = contract_nchunk(g);
     const int lt = g.L[3];
     const size_t ps = contract_part_doubles(g);
     if (sps == P32)
-        hipLaunchKernelGGL((k_contract<P32>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even, s_odd, s_stride,
-                           codes, cpart, nchunk, ps);
+        hipLaunchKernelGGL((k_contract<P32, FIELD>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even, s_odd,
+                           s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps);
     else
-        hipLaunchKernelGGL((k_contract<P64>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even, s_odd, s_stride,
-                           codes, cpart, nchunk, ps);
-    const int m = lt * 288;
-    hipLaunchKernelGGL(k_contract_final, dim3((m + 255) / 256, n), dim3(256), 0, s, cpart, nchunk, lt, raw, ps);
+        hipLaunchKernelGGL((k_contract<P64, FIELD>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even, s_odd,
+                           s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps);
+    const int m = lt * 144;
+    hipLaunchKernelGGL(k_contract_final, dim3((m + 255) / 256, n), dim3(256), 0, s, cpart, nchunk, lt, raw, ps, sr,
+                       si);
+}
+
+void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
+                     size_t s_stride, const uint32_t *codes, double *cpart, const RawOuts &raw, int n, hipStream_t s)
+{
+    contract_t<false>(sps, g, gauge, s_even, s_odd, s_stride, nullptr, nullptr, 0, codes, cpart, raw, n, TM_RSQRT2,
+                      0.0, s);
 }
 
 void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
@@ -277,6 +315,14 @@ void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_ev
     RawOuts R{};
     R.p[0] = raw_out;
     launch_contract(sps, g, gauge, s_even, s_odd, 0, codes, cpart, R, 1, s);
+}
+
+void launch_contract_lr(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
+                        size_t s_stride, const char *l_even, const char *l_odd, size_t l_stride, double *cpart,
+                        const RawOuts &raw, int n, double sr, double si, hipStream_t s)
+{
+    contract_t<true>(sps, g, gauge, s_even, s_odd, s_stride, l_even, l_odd, l_stride, nullptr, cpart, raw, n, sr, si,
+                     s);
 }
 
 // ---------------------------------------------------------------------------

@@ -78,7 +78,9 @@ struct Job {
     int max_iter = 100000;
     int fixed = 0;
     double delta = 0.1;
-    double *raw_out = nullptr;  // noise: device [9][T][16][2]
+    double *raw_out = nullptr;  // noise: device [9][T][16][2] (one-end trick: the isovector part)
+    bool oet = false;           // one-end trick estimators instead of eta^dag G s
+    double *raw_out2 = nullptr; // one-end trick: the isoscalar part [9][T][16][2]
     int want_true = 0;
     // output
     int status = 0;  // tm_status
@@ -106,6 +108,7 @@ struct Batch {
     char *x64 = nullptr, *b64 = nullptr;
     uint32_t *codes = nullptr;
     char *FA = nullptr, *FB = nullptr, *FC = nullptr;  // scratch: FP64 full field [even | odd], or per-slot halves
+    char *FD = nullptr;       // fourth per-slot scratch half (low-precision kinds: one-end trick)
     int wpp = tmk::P64;       // precision of the per-slot scratch halves
     size_t wpitch = 0;        // their slot pitch
     int wslots = 1;           // slots a run may span

@@ -79,6 +79,12 @@ struct RawOuts {
 size_t contract_part_doubles(const Geom &g);
 void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
                      size_t s_stride, const uint32_t *codes, double *cpart, const RawOuts &raw, int n, hipStream_t s);
+// the same with a field as the left vector (the one-end trick): left fields
+// l_even/l_odd + i * l_stride, right fields s_even/s_odd + i * s_stride, all
+// in precision sps; raw = (sr + i si) * the spin-matrix sums
+void launch_contract_lr(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
+                        size_t s_stride, const char *l_even, const char *l_odd, size_t l_stride, double *cpart,
+                        const RawOuts &raw, int n, double sr, double si, hipStream_t s);
 // raw [n][9][T][16][2] -> ops [n][90][T][2]; gtab: [16][4] (col | phase << 2)
 void launch_project(int n, int lt, const double *raw, double *ops, const int *gtab_host, hipStream_t s);
 // TSM combination over per-source ops

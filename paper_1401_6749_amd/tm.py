@@ -116,6 +116,8 @@ _sig = {
     "tm_z4_source": (c_int, [c_void_p, ctypes.POINTER(c_int), c_uint64, c_uint64, c_void_p, c_void_p]),
     "tm_loops_tsm": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_void_p, c_void_p, c_void_p,
                              c_void_p, ctypes.POINTER(tm_tsm_stats)]),
+    "tm_loops_oet": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_void_p, c_void_p, c_void_p,
+                             c_void_p, ctypes.POINTER(tm_tsm_stats)]),
     "tm_project_loops": (c_int, [c_int, c_int, c_void_p, c_void_p]),
     "tm_serve_create": (c_int, [c_void_p, c_int, c_size_t, ctypes.POINTER(c_void_p)]),
     "tm_serve_submit": (c_int, [c_void_p, ctypes.POINTER(tm_request)]),
@@ -316,6 +318,31 @@ def tm_loops_tsm(ctx, gauge, params, lt, want_raw=False, check=True):
         rawc = raw[..., 0] + 1j * raw[..., 1]
         out["raw_hp"] = rawc[: params.n_hp]
         out["raw_lp"] = rawc[params.n_hp:]
+    return out
+
+
+def tm_loops_oet(ctx, gauge, params, lt, want_raw=False, check=True):
+    """One-end trick loops: dict(est_vv, est_ws (90, lt) complex, var_re_vv, var_im_vv, var_re_ws,
+    var_im_ws, optional raw_vv_hp, raw_vv_lp, raw_ws_hp, raw_ws_lp, stats, status)."""
+    est = np.zeros((2, N_OPS, lt, 2))
+    vre = np.zeros((2, N_OPS, lt))
+    vim = np.zeros((2, N_OPS, lt))
+    n_raw = params.n_hp + params.n_hp + params.n_lp
+    raw = np.zeros((2, n_raw, 9, lt, 4, 4, 2)) if want_raw else None
+    st = tm_tsm_stats()
+    rc = _lib.tm_loops_oet(ctx, gauge, ctypes.byref(params), est.ctypes.data, vre.ctypes.data, vim.ctypes.data,
+                           raw.ctypes.data if want_raw else None, ctypes.byref(st))
+    if check:
+        _check(ctx, rc, "tm_loops_oet")
+    out = dict(stats=_stats_dict(st), status=rc)
+    for f, name in enumerate(("vv", "ws")):
+        out["est_" + name] = est[f, ..., 0] + 1j * est[f, ..., 1]
+        out["var_re_" + name] = vre[f]
+        out["var_im_" + name] = vim[f]
+        if want_raw:
+            rawc = raw[f, ..., 0] + 1j * raw[f, ..., 1]
+            out[f"raw_{name}_hp"] = rawc[: params.n_hp]
+            out[f"raw_{name}_lp"] = rawc[params.n_hp:]
     return out
 
 

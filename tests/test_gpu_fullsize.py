@@ -108,3 +108,17 @@ def test_fullsize_loops_matched_iterations(oracle, big):
     for j in (0, 11):
         assert GU.relerr(r64["raw_lp"][j], ref["lp_raw"][j]) < 1e-10, j
         assert GU.relerr(r16["raw_lp"][j], ref["lp_raw"][j]) < 5e-3, j
+
+
+def test_fullsize_loops_oet_f64(oracle, big):
+    """One-end trick spin matrices of one source at 32^3x64 (FP64, five
+    matched iterations) against the oracle, both flavours, to 1e-10."""
+    from paper_1401_6749_amd import tm
+
+    U, g = big
+    ctx = GU.context()
+    ref = oracle.loops_oet(DIMS, -1, U, KAPPA, A, 104, 0, 1, lp_fixed_iters=5, source_ids=[0], return_raw=True)
+    P = tm.tsm_params(KAPPA, A, 104, 0, 1, lp=tm.solver_params("f64", fixed_iters=5), batch=1)
+    r = tm.tm_loops_oet(ctx, g, P, DIMS[3], want_raw=True)
+    for f in ("vv", "ws"):
+        assert GU.relerr(r[f"raw_{f}_lp"][0], ref["raw"]["lp_" + f][0]) < 1e-10, f

@@ -269,3 +269,51 @@ def test_lp_loops_batch_invariant_and_repeatable(half):
         assert np.array_equal(r["raw_hp"], out[0]["raw_hp"])
         assert np.array_equal(r["est"], out[0]["est"])
         assert r["stats"]["lp_iters"] == out[0]["stats"]["lp_iters"]
+
+
+def test_loops_oet_f64_parity(oracle):
+    """One-end trick (Eq. loopVv, Eq. loopStD) on the FP64 path: per-source
+    spin matrices of both flavours and the TSM estimates match the oracle to
+    1e-10 relative, on a lattice whose time extent spans several tiles."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 4, 4, 8)
+    U = inputs.gauge_field(dims, seed=3)
+    g = GU.load(dims, U)
+    kappa, a = 0.12, 0.02
+    n_hp, n_lp = 3, 5
+    P = tm.tsm_params(kappa, a, 201, n_hp, n_lp, hp=tm.solver_params("f64", tol=1e-10),
+                      lp=tm.solver_params("f64", tol=1e-2), batch=4)
+    r = tm.tm_loops_oet(ctx, g, P, dims[3], want_raw=True)
+    ref = oracle.loops_oet(dims, -1, U, kappa, a, 201, n_hp, n_lp, hp_tol=1e-10, lp_tol=1e-2, return_raw=True)
+    for f in ("vv", "ws"):
+        for j in range(n_hp):
+            assert GU.relerr(r[f"raw_{f}_hp"][j], ref["raw"]["hp_" + f][j]) < 1e-10, (f, j)
+        for j in range(n_hp + n_lp):
+            assert GU.relerr(r[f"raw_{f}_lp"][j], ref["raw"]["lp_" + f][j]) < 1e-10, (f, j)
+        assert GU.relerr(r["est_" + f], ref["est_" + f]) < 1e-10, f
+    assert r["stats"]["hp_solves"] == n_hp and r["stats"]["lp_solves"] == n_hp + n_lp
+
+
+@pytest.mark.parametrize("half,tol", [("f16", 5e-3), ("bf16", 3e-2)])
+def test_loops_oet_lp_matched_iterations(oracle, half, tol):
+    """The one-end trick on the half-precision LP path (FP32 reconstruction,
+    D_W and contractions in runs of slots) against the oracle's FP64 solves
+    with the same fixed iteration count; batch 1 and batch 12 give equal bits."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (8, 8, 8, 16)
+    U = inputs.gauge_field(dims, seed=12)
+    g = GU.load(dims, U)
+    kappa, a = 0.1636, 0.0033
+    ref = oracle.loops_oet(dims, -1, U, kappa, a, 5, 0, 12, lp_fixed_iters=5, source_ids=[0, 7], return_raw=True)
+    out = []
+    for batch in (12, 1):
+        P = tm.tsm_params(kappa, a, 5, 0, 12, lp=tm.solver_params("lp", fixed_iters=5, half=half), batch=batch)
+        out.append(tm.tm_loops_oet(ctx, g, P, dims[3], want_raw=True))
+    for f in ("vv", "ws"):
+        for j in (0, 7):
+            assert GU.relerr(out[0][f"raw_{f}_lp"][j], ref["raw"]["lp_" + f][j]) < tol, (f, j)
+        assert np.array_equal(out[0][f"raw_{f}_lp"], out[1][f"raw_{f}_lp"]), f
