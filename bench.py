@@ -201,6 +201,31 @@ def precision_segment(tm, np, ctx, g, W, n_hp=4, n_lp=12):
     return out
 
 
+def oet_segment(tm, np, ctx, g, W, n_hp=12, n_lp=240):
+    """One-end trick (isovector and isoscalar loops with TSM) against the
+    standard eta^dag G s estimator on the same sources: sources/s of both, and
+    for each operator class the median ratio of the TSM variance of the
+    isovector one-end trick estimate (of Tr M_u^-1 X - Tr M_d^-1 X) to that of
+    the standard single-flavour estimate (of Tr M_u^-1 X)."""
+    lt = W["dims"][3]
+    P = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"] + 11, n_hp, n_lp, hp=tm.solver_params("mixed", tol=1e-10),
+                      lp=tm.solver_params("lp", tol=1e-2, half=W["half"]), batch=W["batch"])
+    t0 = time.perf_counter()
+    ro = tm.tm_loops_oet(ctx, g, P, lt)
+    t_oet = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rs = tm.tm_loops_tsm(ctx, g, P, lt)
+    t_std = time.perf_counter() - t0
+    var_o = ro["var_re_vv"] + ro["var_im_vv"]
+    var_s = rs["var_re"] + rs["var_im"]
+    ok = (var_s > 0) & np.isfinite(var_o)
+    ratio = np.where(ok, var_o / np.where(ok, var_s, 1), np.nan)
+    n = n_hp + n_lp
+    return {"sources": n, "oet_sources_per_s": round(n / t_oet, 1), "standard_sources_per_s": round(n / t_std, 1),
+            "isovector_variance_ratio_local_median": float(np.nanmedian(ratio[:16])),
+            "isovector_variance_ratio_deriv_median": float(np.nanmedian(ratio[16:80]))}
+
+
 def r_hp_lp(tm, ctx, g, W, n=12):
     """R_HP/LP: GPU time of n HP sources (solve + contraction) over that of n LP
     sources, from one run with n LP-only sources and one with n HP sources (each
@@ -402,11 +427,14 @@ def main():
 
     roofline = measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)
 
-    precision = rhl = serving = None
+    precision = rhl = serving = oet = None
     if not args.no_extra:
         t0 = time.perf_counter()
         precision = precision_segment(tm, np, ctx, g, W)
         rhl = r_hp_lp(tm, ctx, g, W)
+        oet = oet_segment(tm, np, ctx, g, W)
+        log(f"one-end trick: {oet['oet_sources_per_s']} sources/s vs {oet['standard_sources_per_s']}; "
+            f"isovector variance ratio local {oet['isovector_variance_ratio_local_median']:.2e}")
         log(f"precision and R_HP/LP segments in {time.perf_counter() - t0:.1f}s; R_HP/LP {rhl['value']}")
         if args.serve_requests > 0:
             serving = serving_segment(tm, np, inputs, ctx, g, W, value, args.serve_requests)
@@ -469,6 +497,7 @@ def main():
         "plain_f64": plain,
         "precision": precision,
         "r_hp_lp": rhl,
+        "one_end_trick": oet,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
