@@ -20,6 +20,9 @@ in NumPy:
                                 timeslices (Sec. 2.2), projection and TSM.
   * ``loops_oet``               the same with the one-end trick estimators
                                 (Sec. 2.2, Eq. loopVv and Eq. loopStD).
+  * ``apply_bh`` / ``hpe_exact`` / ``loops_hpe``
+                                the hopping parameter expansion (Sec. 2.4,
+                                Eq. HPE and Eq. loopHPE1).
 
 Array layouts (complex128): spinor (V, 4, 3), gauge (V, 4, 3, 3), with
 lex = x + Lx*(y + Ly*(z + Lz*t)).  ``a`` always means 2*kappa*mu.
@@ -422,5 +425,107 @@ def loops_oet(dims, tbc, U, kappa, a, noise_seed, n_hp, n_lp, hp_tol=1e-10, lp_t
             lpc = np.array([loops["lp_" + f][j] for j in range(n_hp)]).reshape(n_hp, N_OPS, T)
             lpb = np.array([loops["lp_" + f][j] for j in range(n_hp, n_hp + n_lp)]).reshape(n_lp, N_OPS, T)
             est, vre, vim = tsm_combine(hp, lpc, lpb)
+            res.update({"est_" + f: est, "var_re_" + f: vre, "var_im_" + f: vim})
+    return res
+
+
+# ----------------------------------------------------------------------------
+# Hopping parameter expansion (Sec. 2.4, Eq. HPE and Eq. loopHPE1)
+# ----------------------------------------------------------------------------
+_G5_DIAG = np.array([1.0, 1.0, -1.0, -1.0])
+
+
+def apply_bh(dims, tbc, U, kappa, a, psi):
+    """B H psi with M = B^-1 + H: B = (1 + i a g5)^-1 (site-diagonal) and
+    H = -kappa D_hop, the hopping term of M (Sec. 2.4, Eq. HPE)."""
+    h = -kappa * dhop(dims, tbc, U, psi).reshape(-1, 4, 3)
+    return h / (1.0 + 1j * a * _G5_DIAG)[None, :, None]
+
+
+def hpe_exact(dims, kappa, a):
+    """Spin matrices (T, 4, 4) of the exact part of Eq. HPE,
+    K = B - BHB + (BH)^2 B - (BH)^3 B, in the convention of ``contract``:
+    P_ab(t) = sum over x in t and colour of K(x b c; x a c).
+
+    K's site-diagonal blocks follow from the hopping structure alone (Sec. 2.4:
+    independent of the gauge field for local operators):
+      * B is site-diagonal: B = b0 + b5 g5, b0 = 1/(1+a^2), b5 = -i a/(1+a^2);
+      * H (and (BH)^3 B) only links sites an odd number of hops apart, so their
+        diagonal blocks vanish on a lattice with even extents;
+      * (BH)^2 B returns to x through x+mu or x-mu:
+        H(x,x+mu) B H(x+mu,x) = kappa^2 (1 - g_mu) B (1 + g_mu) U U^dag
+                              = 2 kappa^2 b5 g5 (1 + g_mu),
+        the backward hop gives 2 kappa^2 b5 g5 (1 - g_mu); summed over mu,
+        H B H(x,x) = 16 kappa^2 b5 g5, so (BH)^2 B(x,x) = 16 kappa^2 b5 g5 B^2
+        (boundary signs cancel in U U^dag).
+    Hence P(t) = 3 V3 diag_b(B_b + 16 kappa^2 b5 e_b B_b^2), B_b = 1/(1 + i a e_b),
+    e_b = +1, +1, -1, -1.  Valid for even extents >= 4 in every direction
+    (smaller or odd extents close hops around the torus)."""
+    d = _dims(dims)
+    if any(int(L) < 4 or int(L) % 2 for L in d):
+        raise ValueError("hpe_exact needs even extents >= 4")
+    v3 = int(d[0]) * int(d[1]) * int(d[2])
+    b5 = -1j * a / (1.0 + a * a)
+    Bb = 1.0 / (1.0 + 1j * a * _G5_DIAG)
+    k = Bb + 16.0 * kappa * kappa * b5 * _G5_DIAG * Bb * Bb
+    out = np.zeros((int(d[3]), 4, 4), dtype=np.complex128)
+    out[:, np.arange(4), np.arange(4)] = 3 * v3 * k
+    return out
+
+
+def loops_hpe(dims, tbc, U, kappa, a, noise_seed, n_hp, n_lp, hp_tol=1e-10, lp_tol=1e-2,
+              max_iter=100000, lp_fixed_iters=0, source_ids=None, return_raw=False):
+    """Standard and HPE loops from the same solves, with the truncated solver
+    method (Sec. 2.1 and Sec. 2.4).
+
+    For each source s = M^-1 eta: the standard spin matrices contract(eta, s)
+    (as ``loops_tsm``), and the stochastic term of Eq. loopHPE1, the local
+    spin matrix of contract(eta, (BH)^4 s).  The HPE estimate of the 16 local
+    loops is the projection of ``hpe_exact`` plus the TSM combination of the
+    stochastic term; its variance is that of the stochastic term.  Operators
+    with a link (ops 16..89) have a gauge-dependent exact part and are not
+    estimated with the expansion: NaN in est_hpe and its variances.
+    Raw HPE spin matrices are (9, T, 4, 4) with kinds 1..8 zero.
+    """
+    T = int(dims[3])
+    exact_ops = project(np.concatenate([hpe_exact(dims, kappa, a)[None],
+                                        np.zeros((8, T, 4, 4), dtype=np.complex128)]))
+    ids = list(range(n_hp + n_lp)) if source_ids is None else list(source_ids)
+    loops = {"hp_std": {}, "hp_hpe": {}, "lp_std": {}, "lp_hpe": {}}
+    raws = {"hp_std": {}, "hp_hpe": {}, "lp_std": {}, "lp_hpe": {}}
+
+    def one(tag, j, eta, s):
+        w = s
+        for _ in range(4):
+            w = apply_bh(dims, tbc, U, kappa, a, w)
+        P = contract(dims, tbc, U, eta, s)
+        Ph = np.zeros_like(P)
+        Ph[0] = contract(dims, tbc, U, eta, w)[0]
+        raws[tag + "_std"][j], raws[tag + "_hpe"][j] = P, Ph
+        loops[tag + "_std"][j] = project(P)
+        loops[tag + "_hpe"][j] = project(Ph)
+
+    t0 = time.perf_counter()
+    for j in ids:
+        eta = z4_source(dims, noise_seed, j)
+        if j < n_hp:
+            s, _, _, _ = solve(dims, tbc, U, kappa, a, eta, tol=hp_tol, max_iter=max_iter)
+            one("hp", j, eta, s)
+        s, _, _, _ = solve(dims, tbc, U, kappa, a, eta, tol=lp_tol, max_iter=max_iter, fixed_iters=lp_fixed_iters)
+        one("lp", j, eta, s)
+    res = {"seconds": time.perf_counter() - t0, "loops": loops, "exact_ops": exact_ops}
+    if return_raw:
+        res["raw"] = raws
+    if source_ids is None:
+        for f in ("std", "hpe"):
+            hp = np.array([loops["hp_" + f][j] for j in range(n_hp)]).reshape(n_hp, N_OPS, T)
+            lpc = np.array([loops["lp_" + f][j] for j in range(n_hp)]).reshape(n_hp, N_OPS, T)
+            lpb = np.array([loops["lp_" + f][j] for j in range(n_hp, n_hp + n_lp)]).reshape(n_lp, N_OPS, T)
+            est, vre, vim = tsm_combine(hp, lpc, lpb)
+            if f == "hpe":
+                est = est + exact_ops
+                est[N_LOCAL:] = np.nan
+                vre[N_LOCAL:] = np.nan
+                vim[N_LOCAL:] = np.nan
             res.update({"est_" + f: est, "var_re_" + f: vre, "var_im_" + f: vim})
     return res
