@@ -153,10 +153,11 @@ def write_traffic(fetch_db: str, write_db: str, workload: str) -> None:
         "fetch_scale": round(f_fetch, 4), "write_scale": round(f_write, 4),
         "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
         "hbm_bytes_per_launch": round(fetch + write), "dispatches": [nf, nw],
-        "commands": ["rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --roofline-only",
-                     "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -o write -- python3 bench.py --roofline-only",
-                     "python3 bench.py --traffic-from gpurun_out/pmc_fetch/fetch_results.db "
-                     "gpurun_out/pmc_write/write_results.db"],
+        "commands": [f"rocprofv3 --pmc FETCH_SIZE -d {os.path.dirname(fetch_db)} -o fetch -- python3 bench.py "
+                     f"--roofline-only",
+                     f"rocprofv3 --pmc WRITE_SIZE -d {os.path.dirname(write_db)} -o write -- python3 bench.py "
+                     f"--roofline-only",
+                     f"python3 bench.py --traffic-from {fetch_db} {write_db}"],
     }
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
@@ -224,6 +225,32 @@ def oet_segment(tm, np, ctx, g, W, n_hp=12, n_lp=240):
     return {"sources": n, "oet_sources_per_s": round(n / t_oet, 1), "standard_sources_per_s": round(n / t_std, 1),
             "isovector_variance_ratio_local_median": float(np.nanmedian(ratio[:16])),
             "isovector_variance_ratio_deriv_median": float(np.nanmedian(ratio[16:80]))}
+
+
+def hpe_segment(tm, np, ctx, g, W, n_hp=12, n_lp=240):
+    """Hopping parameter expansion of the local loops (with TSM) against the
+    standard estimator: sources/s of tm_loops_hpe (both estimators from the
+    same solves) and of tm_loops_tsm on the same sources, and the median over
+    the 16 local operators and all t of the ratio of the HPE estimate's
+    standard error to the standard one's."""
+    lt = W["dims"][3]
+    P = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"] + 13, n_hp, n_lp, hp=tm.solver_params("mixed", tol=1e-10),
+                      lp=tm.solver_params("lp", tol=1e-2, half=W["half"]), batch=W["batch"])
+    t0 = time.perf_counter()
+    rh = tm.tm_loops_hpe(ctx, g, P, lt)
+    t_hpe = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rs = tm.tm_loops_tsm(ctx, g, P, lt)
+    t_std = time.perf_counter() - t0
+    var_h = (rh["var_re_hpe"] + rh["var_im_hpe"])[:16]
+    var_s = (rh["var_re_std"] + rh["var_im_std"])[:16]
+    ok = var_s > 0
+    ratio = np.sqrt(np.where(ok, var_h / np.where(ok, var_s, 1), np.nan))
+    n = n_hp + n_lp
+    return {"sources": n, "hpe_sources_per_s": round(n / t_hpe, 1), "standard_sources_per_s": round(n / t_std, 1),
+            "same_standard_estimate": bool(np.array_equal(rh["est_std"], rs["est"])),
+            "error_ratio_local_median": float(np.nanmedian(ratio)),
+            "error_ratio_local_range": [float(np.nanmin(ratio)), float(np.nanmax(ratio))]}
 
 
 def r_hp_lp(tm, ctx, g, W, n=12):
@@ -427,7 +454,7 @@ def main():
 
     roofline = measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)
 
-    precision = rhl = serving = oet = None
+    precision = rhl = serving = oet = hpe = None
     if not args.no_extra:
         t0 = time.perf_counter()
         precision = precision_segment(tm, np, ctx, g, W)
@@ -435,6 +462,9 @@ def main():
         oet = oet_segment(tm, np, ctx, g, W)
         log(f"one-end trick: {oet['oet_sources_per_s']} sources/s vs {oet['standard_sources_per_s']}; "
             f"isovector variance ratio local {oet['isovector_variance_ratio_local_median']:.2e}")
+        hpe = hpe_segment(tm, np, ctx, g, W)
+        log(f"HPE: {hpe['hpe_sources_per_s']} sources/s vs {hpe['standard_sources_per_s']}; "
+            f"local error ratio {hpe['error_ratio_local_median']:.2f}")
         log(f"precision and R_HP/LP segments in {time.perf_counter() - t0:.1f}s; R_HP/LP {rhl['value']}")
         if args.serve_requests > 0:
             serving = serving_segment(tm, np, inputs, ctx, g, W, value, args.serve_requests)
@@ -485,9 +515,10 @@ def main():
             "n_hp": W["n_hp"],
             "n_lp": W["n_lp"],
             "hp": "mixed FP32 CG with FP64 reliable updates, tol 1e-10",
-            "lp": (f"{W['half']} storage; Dslash: " + ("f16 spin projection, f16 x f16 products summed in FP32"
-                                                       if W["half"] == "f16" else "FP32 arithmetic")
-                   + "; FP32 vector updates and preparation; truncated at |r|/|r0| = 1e-2"),
+            "lp": (f"{W['half']} storage; Dslash: FP32 arithmetic ("
+                   + ("FP32 FMAs with the f16 operands widened inside the instruction"
+                      if W["half"] == "f16" else "bf16 widened to FP32")
+                   + "); FP32 vector updates and preparation; truncated at |r|/|r0| = 1e-2"),
             "rhs_per_launch": W["batch"],
             "parallelism": "single GPU, whole lattice resident",
         },
@@ -498,6 +529,7 @@ def main():
         "precision": precision,
         "r_hp_lp": rhl,
         "one_end_trick": oet,
+        "hpe": hpe,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -75,7 +75,11 @@ typedef enum tm_op {
     TM_OP_MDAG = 2,         /* out = M^dagger in = gamma5 M(-mu) gamma5 in */
     TM_OP_MHAT = 3,         /* out_e = Mhat in_e */
     TM_OP_MHAT_DAG = 4,     /* out_e = Mhat^dagger in_e */
-    TM_OP_MHAT_DAG_MHAT = 5 /* out_e = Mhat^dagger Mhat in_e */
+    TM_OP_MHAT_DAG_MHAT = 5, /* out_e = Mhat^dagger Mhat in_e */
+    TM_OP_BH = 6             /* out = B H in, full lattice: M = B^-1 + H with
+                                B = (1 + i a gamma5)^-1 and H = -kappa D_hop, the
+                                factor of the hopping parameter expansion (Sec. 2.4,
+                                Eq. HPE) */
 } tm_op;
 
 /* Solver modes (Sec. 2.1: low- and high-precision inversions by CG). */
@@ -280,6 +284,29 @@ int tm_loops_tsm(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *pa
  * one more Dslash application (D_W s) and one more contraction than
  * tm_loops_tsm.  Errors as tm_loops_tsm. */
 int tm_loops_oet(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *params, double *est,
+                 double *var_re, double *var_im, double *raw, tm_tsm_stats *stats);
+
+/* The same sources, solves and TSM combination with the hopping parameter
+ * expansion (Sec. 2.4, Eq. HPE and Eq. loopHPE1) of the 16 local loops.
+ * With M = B^-1 + H, B = (1 + i a g5)^-1 and H = -kappa D_hop,
+ *   M^-1 = B - BHB + (BH)^2 B - (BH)^3 B + (BH)^4 M^-1;
+ * the first four terms are traced exactly (for local G their site-diagonal
+ * blocks do not depend on the links: 3 V3 diag_b(B_b + 16 kappa^2 b5 e_b
+ * B_b^2), b5 = -i a/(1 + a^2), e_b = g5's eigenvalue on spin b) and the last
+ * stochastically as eta^dag G (BH)^4 s with s = M^-1 eta.
+ *   flavour 0: the standard estimator, identical to tm_loops_tsm;
+ *   flavour 1: the expansion: ops 0..15 = exact part + TSM combination of
+ *              eta^dag G (BH)^4 s, variances those of the stochastic term;
+ *              ops 16..89 (operators with a link, whose exact part depends
+ *              on the links) are NaN.
+ * Outputs as tm_loops_oet: est [2][TM_N_OPS][Lt][2], var_re/var_im
+ * [2][TM_N_OPS][Lt], raw (optional) [2][n_hp + n_hp + n_lp][9][Lt][4][4][2]
+ * where flavour 1 holds eta^dag (BH)^4 s in kind 0 and zeros in kinds 1..8.
+ * Each source costs four more full-lattice B H applications and one local
+ * contraction.  Every extent must be >= 4 (TM_ERR_ARG otherwise: smaller
+ * tori close two- and three-hop paths through the links).  Errors as
+ * tm_loops_tsm. */
+int tm_loops_hpe(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *params, double *est,
                  double *var_re, double *var_im, double *raw, tm_tsm_stats *stats);
 
 /* Project spin matrices [n][9][Lt][4][4][2] (host) onto the 90 operator

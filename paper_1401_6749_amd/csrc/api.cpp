@@ -375,7 +375,7 @@ extern "C" int tm_dslash(tm_context *ctx, const tm_gauge *G, tm_op op, double ka
     const int p = prec_index(prec);
     if (!ctx) return TM_ERR_ARG;
     if (!G || p < 0) return set_err(ctx, TM_ERR_ARG, "tm_dslash: bad gauge or precision");
-    const bool full = op == TM_OP_HOP || op == TM_OP_M || op == TM_OP_MDAG;
+    const bool full = op == TM_OP_HOP || op == TM_OP_M || op == TM_OP_MDAG || op == TM_OP_BH;
     const size_t fb = half_bytes(p, G->g) * (full ? 2 : 1);
     return tm_dslash_ex(ctx, G, op, kappa, a, prec, nrhs, in, fb, out, fb, hip_stream);
 }
@@ -390,10 +390,10 @@ extern "C" int tm_dslash_ex(tm_context *ctx, const tm_gauge *G, tm_op op, double
     if (!(G->precs & (1u << p))) return set_err(ctx, TM_ERR_ARG, "tm_dslash: gauge not loaded in this precision");
     if (nrhs < 1 || nrhs > MAX_SLOTS) return set_err(ctx, TM_ERR_ARG, "tm_dslash: nrhs must be 1..%d", MAX_SLOTS);
     if (!in || !out) return set_err(ctx, TM_ERR_ARG, "tm_dslash: null field");
-    if (op < TM_OP_HOP || op > TM_OP_MHAT_DAG_MHAT) return set_err(ctx, TM_ERR_ARG, "tm_dslash: unknown op");
+    if (op < TM_OP_HOP || op > TM_OP_BH) return set_err(ctx, TM_ERR_ARG, "tm_dslash: unknown op");
     const Geom &g = G->g;
     const size_t hb = half_bytes(p, g);
-    const bool full = op == TM_OP_HOP || op == TM_OP_M || op == TM_OP_MDAG;
+    const bool full = op == TM_OP_HOP || op == TM_OP_M || op == TM_OP_MDAG || op == TM_OP_BH;
     const size_t fb = full ? 2 * hb : hb;
     if (in_stride < fb || out_stride < fb || in_stride % 16 || out_stride % 16)
         return set_err(ctx, TM_ERR_ARG, "tm_dslash: strides must be multiples of 16 and at least one field");
@@ -413,9 +413,9 @@ extern "C" int tm_dslash_ex(tm_context *ctx, const tm_gauge *G, tm_op op, double
     const char *ic = (const char *)in;
     char *oc = (char *)out;
     if (full) {
-        const int coef = op == TM_OP_HOP ? CM_HOP : op == TM_OP_M ? CM_M : CM_MDAG;
+        const int coef = op == TM_OP_HOP ? CM_HOP : op == TM_OP_M ? CM_M : op == TM_OP_BH ? CM_BH : CM_MDAG;
         const bool dag = op == TM_OP_MDAG;
-        const bool in2 = op != TM_OP_HOP;
+        const bool in2 = op == TM_OP_M || op == TM_OP_MDAG;
         for (int par = 0; par < 2; par++) {
             A.in = ic + (1 - par) * hb;
             A.in2_slot = in_stride;
@@ -621,8 +621,11 @@ extern "C" int tm_project_loops(int n, int lt, const double *raw, double *ops)
 // ---------------------------------------------------------------------------
 // loops with the truncated solver method
 // ---------------------------------------------------------------------------
+// estimators of tsm_run: eta^dag G s; the one-end trick (isovector, isoscalar);
+// eta^dag G s and the hopping parameter expansion from the same solves
+enum Est { EST_STD = 0, EST_OET = 1, EST_HPE = 2 };
 int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *vre, double *vim,
-            double *raw_host, tm_tsm_stats *stats, bool oet = false);
+            double *raw_host, tm_tsm_stats *stats, Est mode = EST_STD);
 
 extern "C" int tm_loops_tsm(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *var_re,
                             double *var_im, double *raw, tm_tsm_stats *stats)
@@ -635,7 +638,18 @@ extern "C" int tm_loops_oet(tm_context *ctx, const tm_gauge *G, const tm_tsm_par
                             double *var_im, double *raw, tm_tsm_stats *stats)
 {
     if (!ctx) return TM_ERR_ARG;
-    return tsm_run(ctx, G, P, est, var_re, var_im, raw, stats, true);
+    return tsm_run(ctx, G, P, est, var_re, var_im, raw, stats, EST_OET);
+}
+
+extern "C" int tm_loops_hpe(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *var_re,
+                            double *var_im, double *raw, tm_tsm_stats *stats)
+{
+    if (!ctx) return TM_ERR_ARG;
+    if (G && G->ctx == ctx)
+        for (int d = 0; d < 4; d++)
+            if (G->dims[d] < 4)
+                return set_err(ctx, TM_ERR_ARG, "tm_loops_hpe: every extent must be >= 4 (got %d)", G->dims[d]);
+    return tsm_run(ctx, G, P, est, var_re, var_im, raw, stats, EST_HPE);
 }
 
 // insertion tables of the one-end trick: g5 G (flavour 0) and g5 G g5 (flavour 1),
@@ -667,8 +681,9 @@ int tsm_check(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P)
 }
 
 int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *vre, double *vim,
-            double *raw_host, tm_tsm_stats *stats, bool oet)
+            double *raw_host, tm_tsm_stats *stats, Est mode)
 {
+    const bool oet = mode == EST_OET, hpe = mode == EST_HPE;
     if (!est || !vre || !vim) return set_err(ctx, TM_ERR_ARG, "tm_loops: null output");
     int rc = tsm_check(ctx, G, P);
     if (rc) return rc;
@@ -677,13 +692,24 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
     const double t0 = now_s();
     const int lt = G->dims[3];
     const int n_hp = P->n_hp, n_lpt = P->n_hp + P->n_lp;
-    const int nf = oet ? 2 : 1;  // estimators: eta^dag G s, or the isovector and isoscalar one-end trick
+    // estimators: eta^dag G s; the isovector and isoscalar one-end trick; or
+    // eta^dag G s and the expansion's stochastic term eta^dag G (BH)^4 s
+    const int nf = mode == EST_STD ? 1 : 2;
     const size_t raw_per = (size_t)9 * lt * 32;  // doubles per source
     const size_t ops_per = (size_t)TM_N_OPS * lt * 2;
     const size_t src_raw = (size_t)(n_hp + n_lpt) * raw_per, src_ops = (size_t)(n_hp + n_lpt) * ops_per;
-    const size_t dev_doubles = nf * (src_raw + src_ops + ops_per * 2);
+    const size_t dev_doubles = nf * (src_raw + src_ops + ops_per * 2) + (hpe ? raw_per + ops_per : 0);
     double *dbuf = (double *)dalloc(ctx, dev_doubles * sizeof(double));
     if (!dbuf) return set_err(ctx, TM_ERR_NOMEM, "tm_loops: no memory for per-source loops");
+    // the expansion's raw spin matrices carry the local kind only
+    if (hpe) {
+        hipError_t e = hipMemsetAsync(dbuf, 0, dev_doubles * sizeof(double), nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) {
+            dfree(ctx, dbuf);
+            return set_err(ctx, TM_ERR_HIP, "tm_loops_hpe: clearing the loop buffers: %s", hipGetErrorString(e));
+        }
+    }
     // flavour f: raw [n_hp | n_lpt] sources, ops likewise, then est and variances
     auto raw_hp = [&](int f) { return dbuf + f * src_raw; };
     auto raw_lp = [&](int f) { return raw_hp(f) + n_hp * raw_per; };
@@ -692,6 +718,7 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
     auto ops_lp = [&](int f) { return ops_hp(f) + n_hp * ops_per; };
     double *estb = opsb + nf * src_ops;
     auto d_est = [&](int f) { return estb + f * 2 * ops_per; };
+    double *raw_exact = estb + nf * 2 * ops_per, *ops_exact = raw_exact + raw_per;  // HPE only
     std::vector<Job> hp(n_hp), lp(n_lpt);
     std::vector<Job *> qh, ql;
     for (int i = 0; i < n_hp; i++) {
@@ -702,7 +729,8 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         job_from(j, P->hp, P->kappa, P->two_kappa_mu);
         j.raw_out = raw_hp(0) + i * raw_per;
         j.oet = oet;
-        j.raw_out2 = oet ? raw_hp(1) + i * raw_per : nullptr;
+        j.hpe = hpe;
+        j.raw_out2 = nf > 1 ? raw_hp(1) + i * raw_per : nullptr;
         j.want_true = P->want_true_resid;
         j.hp = true;
         qh.push_back(&j);
@@ -715,7 +743,8 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         job_from(j, P->lp, P->kappa, P->two_kappa_mu);
         j.raw_out = raw_lp(0) + i * raw_per;
         j.oet = oet;
-        j.raw_out2 = oet ? raw_lp(1) + i * raw_per : nullptr;
+        j.hpe = hpe;
+        j.raw_out2 = nf > 1 ? raw_lp(1) + i * raw_per : nullptr;
         j.want_true = P->want_true_resid;
         ql.push_back(&j);
     }
@@ -747,14 +776,20 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         for (hipStream_t x : streams) hipStreamSynchronize(x);
         int tv[64], tw[64];
         if (oet) oet_gamma_tables(tv, tw);
+        if (hpe) {
+            launch_hpe_exact(G->g, P->kappa, P->two_kappa_mu, raw_exact, s);
+            launch_project(1, lt, raw_exact, ops_exact, gamma_table(), s);
+        }
         hipError_t e = hipSuccess;
         for (int f = 0; f < nf && e == hipSuccess; f++) {
             const int *gt = !oet ? gamma_table() : f == 0 ? tv : tw;
             double *de = d_est(f), *dvre = de + ops_per, *dvim = dvre + ops_per / 2;
             launch_project(n_hp, lt, raw_hp(f), ops_hp(f), gt, s);
             launch_project(n_lpt, lt, raw_lp(f), ops_lp(f), gt, s);
+            // HPE flavour: exact part added to the 16 local loops, the others undefined
+            const bool hf = hpe && f == 1;
             launch_tsm_combine(n_hp, P->n_lp, lt, ops_hp(f), ops_lp(f), ops_lp(f) + (size_t)n_hp * ops_per, de, dvre,
-                               dvim, s);
+                               dvim, s, hf ? ops_exact : nullptr, hf ? 16 : 90);
             e = hipMemcpyAsync(est + f * ops_per, de, ops_per * sizeof(double), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(vre + f * ops_per / 2, dvre, ops_per / 2 * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -598,7 +598,22 @@ static void harvest_lp_run(Batch *b, int s0, int n)
         launch_contract_lr(P32, g, b->G->links[P32], re, ro, w, se32, so32, w, b->cpart, R2, n, 2.0, 0.0, s);
         return;
     }
-    launch_contract(P32, g, b->G->links[P32], se32, so32, w, b->codes + (size_t)s0 * 2 * g.vh, b->cpart, R, n, s);
+    const uint32_t *codes = b->codes + (size_t)s0 * 2 * g.vh;
+    launch_contract(P32, g, b->G->links[P32], se32, so32, w, codes, b->cpart, R, n, s);
+    if (j->hpe) {
+        // (BH)^4 s: even part ((BH)_eo (BH)_oe)^2 s_e via FA (odd) into FD,
+        // odd part ((BH)_oe (BH)_eo)^2 s_o via FA (even) into FB
+        char *ta = b->FA, *we = b->FD, *wo = b->FB;
+        dsl_run(b, P32, false, EPI_PLAIN, CM_BH, 1, se32, w, nullptr, 0, ta, w, j->kappa, j->a, n);
+        dsl_run(b, P32, false, EPI_PLAIN, CM_BH, 0, ta, w, nullptr, 0, we, w, j->kappa, j->a, n);
+        dsl_run(b, P32, false, EPI_PLAIN, CM_BH, 1, we, w, nullptr, 0, ta, w, j->kappa, j->a, n);
+        dsl_run(b, P32, false, EPI_PLAIN, CM_BH, 0, ta, w, nullptr, 0, we, w, j->kappa, j->a, n);
+        dsl_run(b, P32, false, EPI_PLAIN, CM_BH, 0, so32, w, nullptr, 0, ta, w, j->kappa, j->a, n);
+        dsl_run(b, P32, false, EPI_PLAIN, CM_BH, 1, ta, w, nullptr, 0, wo, w, j->kappa, j->a, n);
+        dsl_run(b, P32, false, EPI_PLAIN, CM_BH, 0, wo, w, nullptr, 0, ta, w, j->kappa, j->a, n);
+        dsl_run(b, P32, false, EPI_PLAIN, CM_BH, 1, ta, w, nullptr, 0, wo, w, j->kappa, j->a, n);
+        launch_contract_local(P32, g, we, wo, w, codes, b->cpart, R2, n, s);
+    }
 }
 
 // results of a finished slot: status, counts, optional true residual; frees the slot
@@ -665,8 +680,23 @@ static void harvest64(Batch *b, int slot, const SlotState &S, Job *j)
             launch_contract_lr(P64, g, b->G->links[P64], se, so, 0, se, so, 0, b->cpart, R, 1, 0.0, -2.0 * j->a, s);
             launch_contract_lr(P64, g, b->G->links[P64], re, ro, 0, se, so, 0, b->cpart, R2, 1, 2.0, 0.0, s);
         } else if (j->raw_out) {
-            launch_contract(P64, g, b->G->links[P64], se, so, b->codes + (size_t)slot * 2 * g.vh, b->cpart,
-                            j->raw_out, s);
+            const uint32_t *codes = b->codes + (size_t)slot * 2 * g.vh;
+            launch_contract(P64, g, b->G->links[P64], se, so, codes, b->cpart, j->raw_out, s);
+            if (j->hpe) {
+                // (BH)^4 s into FB = [even | odd] through FA (see harvest_lp_run)
+                char *ae = b->FA, *ao = b->FA + b->h64, *we = b->FB, *wo = b->FB + b->h64;
+                d64(b, false, EPI_PLAIN, CM_BH, 1, se, nullptr, ao, j->kappa, j->a);
+                d64(b, false, EPI_PLAIN, CM_BH, 0, ao, nullptr, we, j->kappa, j->a);
+                d64(b, false, EPI_PLAIN, CM_BH, 1, we, nullptr, ao, j->kappa, j->a);
+                d64(b, false, EPI_PLAIN, CM_BH, 0, ao, nullptr, we, j->kappa, j->a);
+                d64(b, false, EPI_PLAIN, CM_BH, 0, so, nullptr, ae, j->kappa, j->a);
+                d64(b, false, EPI_PLAIN, CM_BH, 1, ae, nullptr, wo, j->kappa, j->a);
+                d64(b, false, EPI_PLAIN, CM_BH, 0, wo, nullptr, ae, j->kappa, j->a);
+                d64(b, false, EPI_PLAIN, CM_BH, 1, ae, nullptr, wo, j->kappa, j->a);
+                RawOuts R2{};
+                R2.p[0] = j->raw_out2;
+                launch_contract_local(P64, g, we, wo, 0, codes, b->cpart, R2, 1, s);
+            }
         }
     } else {
         load_eta(b, slot, j);
@@ -738,7 +768,8 @@ int batch_process(Batch *b, std::vector<Job *> &finished)
         if (lp_harvest(b, j)) {
             static const int cap = run_cap("TM_HARVEST_RUN");
             while (s + n < S && n < std::min(b->wslots, cap) && done(s + n) && lp_harvest(b, b->slot_job[s + n]) &&
-                   same_params(b->slot_job[s + n], j) && b->slot_job[s + n]->oet == j->oet)
+                   same_params(b->slot_job[s + n], j) && b->slot_job[s + n]->oet == j->oet &&
+                   b->slot_job[s + n]->hpe == j->hpe)
                 n++;
             harvest_lp_run(b, s, n);
         } else if (prep_prec(b, j) != P32) {

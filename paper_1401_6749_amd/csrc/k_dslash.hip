@@ -446,6 +446,7 @@ __device__ __forceinline__ void coefs(int mode, double kappa, double a, cpx<T> P
         case CM_RECON: pr = den; pi = -ch * a * den; qr = kappa * den; qi = -kappa * ch * a * den; break;
         case CM_M: pr = 1; pi = ch * a; qr = -kappa; break;
         case CM_MDAG: pr = 1; pi = -ch * a; qr = -kappa; break;
+        case CM_BH: qr = -kappa * den; qi = kappa * ch * a * den; break;
         default: break;
         }
         P[c] = cpx<T>{(T)pr, (T)pi};

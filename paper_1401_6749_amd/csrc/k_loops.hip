@@ -228,8 +228,8 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
 
 // partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
 // blockIdx.y = source; the left vector is the source's codes (FIELD false) or
-// the field pair (l_even, l_odd) + i * l_stride
-template <int SPS, bool FIELD>
+// the field pair (l_even, l_odd) + i * l_stride; NK = 9 (all kinds) or 1 (local only)
+template <int SPS, bool FIELD, int NK>
 __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd,
                                                  size_t s_stride, const char *l_even, const char *l_odd,
                                                  size_t l_stride, const uint32_t *codes, double *cpart, int nchunk,
@@ -249,26 +249,29 @@ __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const ch
     contract_kind<K, SPS, FIELD>(g, G, s_fld, left, t, chunk, acc);     \
     block_write<32>(acc, lds, dst + (K) * 32);
     TMK_KIND(0)
-    TMK_KIND(1)
-    TMK_KIND(2)
-    TMK_KIND(3)
-    TMK_KIND(4)
-    TMK_KIND(5)
-    TMK_KIND(6)
-    TMK_KIND(7)
-    TMK_KIND(8)
+    if constexpr (NK == 9) {
+        TMK_KIND(1)
+        TMK_KIND(2)
+        TMK_KIND(3)
+        TMK_KIND(4)
+        TMK_KIND(5)
+        TMK_KIND(6)
+        TMK_KIND(7)
+        TMK_KIND(8)
+    }
 #undef TMK_KIND
 }
 
-// raw[kind][t][ab] = (sr + i si) * sum_chunk cpart[t][chunk][kind][ab] (complex); blockIdx.y = source
+// raw[kind][t][ab] = (sr + i si) * sum_chunk cpart[t][chunk][kind][ab] (complex) for the
+// first nk kinds; blockIdx.y = source
 __global__ void k_contract_final(const double *cpart, int nchunk, int lt, RawOuts R, size_t part_stride, double sr,
-                                 double si)
+                                 double si, int nk)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over lt * 144 complex entries
-    if (i >= lt * 144) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over lt * nk * 16 complex entries
+    if (i >= lt * nk * 16) return;
     cpart += (size_t)blockIdx.y * part_stride;
     double *raw = R.p[blockIdx.y];
-    const int t = i / 144, e = 2 * (i - t * 144);
+    const int t = i / (nk * 16), e = 2 * (i - t * nk * 16);
     double re = 0.0, im = 0.0;
     for (int c = 0; c < nchunk; c++) {
         re += cpart[((size_t)t * nchunk + c) * 288 + e];
@@ -281,7 +284,7 @@ __global__ void k_contract_final(const double *cpart, int nchunk, int lt, RawOut
 
 size_t contract_part_doubles(const Geom &g) { return (size_t)g.L[3] * contract_nchunk(g) * 288; }
 
-template <bool FIELD>
+template <bool FIELD, int NK = 9>
 static void contract_t(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
                        size_t s_stride, const char *l_even, const char *l_odd, size_t l_stride,
                        const uint32_t *codes, double *cpart, const RawOuts &raw, int n, double sr, double si,
@@ -292,14 +295,14 @@ static void contract_t(int sps, const Geom &g, const void *gauge, const char *s_
     const int lt = g.L[3];
     const size_t ps = contract_part_doubles(g);
     if (sps == P32)
-        hipLaunchKernelGGL((k_contract<P32, FIELD>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even, s_odd,
-                           s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps);
+        hipLaunchKernelGGL((k_contract<P32, FIELD, NK>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even,
+                           s_odd, s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps);
     else
-        hipLaunchKernelGGL((k_contract<P64, FIELD>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even, s_odd,
-                           s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps);
-    const int m = lt * 144;
+        hipLaunchKernelGGL((k_contract<P64, FIELD, NK>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even,
+                           s_odd, s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps);
+    const int m = lt * NK * 16;
     hipLaunchKernelGGL(k_contract_final, dim3((m + 255) / 256, n), dim3(256), 0, s, cpart, nchunk, lt, raw, ps, sr,
-                       si);
+                       si, NK);
 }
 
 void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
@@ -323,6 +326,49 @@ void launch_contract_lr(int sps, const Geom &g, const void *gauge, const char *s
 {
     contract_t<true>(sps, g, gauge, s_even, s_odd, s_stride, l_even, l_odd, l_stride, nullptr, cpart, raw, n, sr, si,
                      s);
+}
+
+void launch_contract_local(int sps, const Geom &g, const char *s_even, const char *s_odd, size_t s_stride,
+                           const uint32_t *codes, double *cpart, const RawOuts &raw, int n, hipStream_t s)
+{
+    contract_t<false, 1>(sps, g, nullptr, s_even, s_odd, s_stride, nullptr, nullptr, 0, codes, cpart, raw, n,
+                         TM_RSQRT2, 0.0, s);
+}
+
+// ---------------------------------------------------------------------------
+// Exact part of the hopping parameter expansion (Sec. 2.4, Eq. HPE) as local
+// spin matrices raw[0][t][a][b] (kinds 1..8 untouched): the site-diagonal
+// blocks of B - BHB + (BH)^2 B - (BH)^3 B summed over a timeslice and colour.
+// With B = b0 + b5 g5 (b5 = -i a / (1 + a^2)) and H = -kappa D_hop: odd
+// powers of H never return to a site of a lattice with even extents; the two
+// ways of returning in two hops along +-mu give (1 -+ g_mu) B (1 +- g_mu)
+// kappa^2 = 2 kappa^2 b5 g5 (1 +- g_mu), which sum over mu to 16 kappa^2 b5 g5,
+// independent of the links.  So the block is diag_b(B_b + 16 kappa^2 b5 e_b
+// B_b^2) times 3 V3, B_b = 1/(1 + i a e_b), e_b = g5's eigenvalue on spin b.
+// ---------------------------------------------------------------------------
+__global__ void k_hpe_exact(int lt, double v3, double kappa, double a, double *raw)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over lt * 16 entries
+    if (i >= lt * 16) return;
+    const int ab = i & 15, al = ab >> 2, be = ab & 3;
+    double re = 0.0, im = 0.0;
+    if (al == be) {
+        const double e = be < 2 ? 1.0 : -1.0, den = 1.0 / (1.0 + a * a);
+        const double br = den, bi = -e * a * den;                       // B_b
+        const double b2r = br * br - bi * bi, b2i = 2.0 * br * bi;      // B_b^2
+        const double cr = 0.0, ci = -16.0 * kappa * kappa * a * den * e;  // 16 kappa^2 b5 e_b
+        re = 3.0 * v3 * (br + cr * b2r - ci * b2i);
+        im = 3.0 * v3 * (bi + cr * b2i + ci * b2r);
+    }
+    raw[2 * i] = re;
+    raw[2 * i + 1] = im;
+}
+
+void launch_hpe_exact(const Geom &g, double kappa, double a, double *raw, hipStream_t s)
+{
+    const int lt = g.L[3];
+    hipLaunchKernelGGL(k_hpe_exact, dim3((lt * 16 + 255) / 256), dim3(256), 0, s, lt,
+                       (double)g.L[0] * g.L[1] * g.L[2], kappa, a, raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -442,26 +488,31 @@ __device__ __forceinline__ void mean_var(int n, const double *a, const double *b
 }
 
 __global__ void k_tsm(int n_hp, int n_lp, int lt, const double *hp, const double *lpc, const double *lpb,
-                      double *est, double *vre, double *vim)
+                      double *est, double *vre, double *vim, const double *add, int nvalid)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over 90 * lt
     if (i >= 90 * lt) return;
+    if (i >= nvalid * lt) {
+        est[2 * i] = est[2 * i + 1] = vre[i] = vim[i] = __builtin_nan("");
+        return;
+    }
     const size_t stride = (size_t)90 * lt * 2, off = (size_t)2 * i;
     double m1[2], v1[2], m2[2], v2[2];
     mean_var(n_hp, hp, lpc, stride, off, m1, v1);
     mean_var(n_lp, lpb, nullptr, stride, off, m2, v2);
-    est[2 * i] = m1[0] + m2[0];
-    est[2 * i + 1] = m1[1] + m2[1];
+    est[2 * i] = m1[0] + m2[0] + (add ? add[2 * i] : 0.0);
+    est[2 * i + 1] = m1[1] + m2[1] + (add ? add[2 * i + 1] : 0.0);
     vre[i] = v1[0] + v2[0];
     vim[i] = v1[1] + v2[1];
 }
 
 void launch_tsm_combine(int n_hp, int n_lp, int lt, const double *ops_hp, const double *ops_lp_corr,
-                        const double *ops_lp_bulk, double *est, double *var_re, double *var_im, hipStream_t s)
+                        const double *ops_lp_bulk, double *est, double *var_re, double *var_im, hipStream_t s,
+                        const double *ops_add, int nvalid)
 {
     const int n = 90 * lt;
     hipLaunchKernelGGL(k_tsm, dim3((n + 127) / 128), dim3(128), 0, s, n_hp, n_lp, lt, ops_hp, ops_lp_corr,
-                       ops_lp_bulk, est, var_re, var_im);
+                       ops_lp_bulk, est, var_re, var_im, ops_add, nvalid);
 }
 
 }  // namespace tmk

@@ -80,7 +80,8 @@ struct Job {
     double delta = 0.1;
     double *raw_out = nullptr;  // noise: device [9][T][16][2] (one-end trick: the isovector part)
     bool oet = false;           // one-end trick estimators instead of eta^dag G s
-    double *raw_out2 = nullptr; // one-end trick: the isoscalar part [9][T][16][2]
+    double *raw_out2 = nullptr; // one-end trick: the isoscalar part; HPE: eta^dag G (BH)^4 s (kind 0) [9][T][16][2]
+    bool hpe = false;           // also the stochastic term of the hopping parameter expansion
     int want_true = 0;
     // output
     int status = 0;  // tm_status

@@ -85,11 +85,20 @@ void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_ev
 void launch_contract_lr(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
                         size_t s_stride, const char *l_even, const char *l_odd, size_t l_stride, double *cpart,
                         const RawOuts &raw, int n, double sr, double si, hipStream_t s);
+// local spin matrices only (kind 0 of raw[i]; other kinds untouched) of n
+// sources with Z4-code left vectors, as launch_contract
+void launch_contract_local(int sps, const Geom &g, const char *s_even, const char *s_odd, size_t s_stride,
+                           const uint32_t *codes, double *cpart, const RawOuts &raw, int n, hipStream_t s);
+// exact part of the hopping parameter expansion as local spin matrices
+// raw[0][T][16][2] (kinds 1..8 untouched); even extents >= 4
+void launch_hpe_exact(const Geom &g, double kappa, double a, double *raw, hipStream_t s);
 // raw [n][9][T][16][2] -> ops [n][90][T][2]; gtab: [16][4] (col | phase << 2)
 void launch_project(int n, int lt, const double *raw, double *ops, const int *gtab_host, hipStream_t s);
-// TSM combination over per-source ops
+// TSM combination over per-source ops; est += ops_add when given; ops from
+// nvalid on are NaN (estimate and variances)
 void launch_tsm_combine(int n_hp, int n_lp, int lt, const double *ops_hp, const double *ops_lp_corr,
-                        const double *ops_lp_bulk, double *est, double *var_re, double *var_im, hipStream_t s);
+                        const double *ops_lp_bulk, double *est, double *var_re, double *var_im, hipStream_t s,
+                        const double *ops_add = nullptr, int nvalid = 90);
 
 // ---- layout ----
 // canonical FP64 gauge (device) -> per-precision link arrays

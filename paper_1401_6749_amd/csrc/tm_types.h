@@ -95,7 +95,8 @@ enum : int {
     CM_PREP = 5,      // P = 1, Q = kappa
     CM_RECON = 6,     // P = A^-1, Q = kappa A^-1
     CM_M = 7,         // P = A, Q = -kappa
-    CM_MDAG = 8       // P = A^dagger, Q = -kappa
+    CM_MDAG = 8,      // P = A^dagger, Q = -kappa
+    CM_BH = 9         // P = 0, Q = -kappa A^-1   (B H of the hopping parameter expansion)
 };
 
 // Epilogues of the Dslash kernel

@@ -51,7 +51,7 @@ TM_OK, TM_ERR_ARG, TM_ERR_NOMEM, TM_ERR_HIP, TM_ERR_NOCONV, TM_ERR_NUMERIC, TM_E
 STATUS_NAMES = {0: "TM_OK", -1: "TM_ERR_ARG", -2: "TM_ERR_NOMEM", -3: "TM_ERR_HIP", -4: "TM_ERR_NOCONV",
                 -5: "TM_ERR_NUMERIC", -6: "TM_ERR_STATE"}
 PREC = {"f64": 1, "f32": 2, "f16": 4, "bf16": 8}
-OPS = {"hop": 0, "m": 1, "mdag": 2, "mhat": 3, "mhat_dag": 4, "mhat_dag_mhat": 5}
+OPS = {"hop": 0, "m": 1, "mdag": 2, "mhat": 3, "mhat_dag": 4, "mhat_dag_mhat": 5, "bh": 6}
 MODES = {"f64": 0, "mixed": 1, "lp": 2}
 N_OPS = 90
 
@@ -117,6 +117,8 @@ _sig = {
     "tm_loops_tsm": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_void_p, c_void_p, c_void_p,
                              c_void_p, ctypes.POINTER(tm_tsm_stats)]),
     "tm_loops_oet": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_void_p, c_void_p, c_void_p,
+                             c_void_p, ctypes.POINTER(tm_tsm_stats)]),
+    "tm_loops_hpe": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_void_p, c_void_p, c_void_p,
                              c_void_p, ctypes.POINTER(tm_tsm_stats)]),
     "tm_project_loops": (c_int, [c_int, c_int, c_void_p, c_void_p]),
     "tm_serve_create": (c_int, [c_void_p, c_int, c_size_t, ctypes.POINTER(c_void_p)]),
@@ -321,21 +323,19 @@ def tm_loops_tsm(ctx, gauge, params, lt, want_raw=False, check=True):
     return out
 
 
-def tm_loops_oet(ctx, gauge, params, lt, want_raw=False, check=True):
-    """One-end trick loops: dict(est_vv, est_ws (90, lt) complex, var_re_vv, var_im_vv, var_re_ws,
-    var_im_ws, optional raw_vv_hp, raw_vv_lp, raw_ws_hp, raw_ws_lp, stats, status)."""
+def _loops2(fn, names, ctx, gauge, params, lt, want_raw, check):
     est = np.zeros((2, N_OPS, lt, 2))
     vre = np.zeros((2, N_OPS, lt))
     vim = np.zeros((2, N_OPS, lt))
     n_raw = params.n_hp + params.n_hp + params.n_lp
     raw = np.zeros((2, n_raw, 9, lt, 4, 4, 2)) if want_raw else None
     st = tm_tsm_stats()
-    rc = _lib.tm_loops_oet(ctx, gauge, ctypes.byref(params), est.ctypes.data, vre.ctypes.data, vim.ctypes.data,
+    rc = getattr(_lib, fn)(ctx, gauge, ctypes.byref(params), est.ctypes.data, vre.ctypes.data, vim.ctypes.data,
                            raw.ctypes.data if want_raw else None, ctypes.byref(st))
     if check:
-        _check(ctx, rc, "tm_loops_oet")
+        _check(ctx, rc, fn)
     out = dict(stats=_stats_dict(st), status=rc)
-    for f, name in enumerate(("vv", "ws")):
+    for f, name in enumerate(names):
         out["est_" + name] = est[f, ..., 0] + 1j * est[f, ..., 1]
         out["var_re_" + name] = vre[f]
         out["var_im_" + name] = vim[f]
@@ -344,6 +344,20 @@ def tm_loops_oet(ctx, gauge, params, lt, want_raw=False, check=True):
             out[f"raw_{name}_hp"] = rawc[: params.n_hp]
             out[f"raw_{name}_lp"] = rawc[params.n_hp:]
     return out
+
+
+def tm_loops_oet(ctx, gauge, params, lt, want_raw=False, check=True):
+    """One-end trick loops: dict(est_vv, est_ws (90, lt) complex, var_re_vv, var_im_vv, var_re_ws,
+    var_im_ws, optional raw_vv_hp, raw_vv_lp, raw_ws_hp, raw_ws_lp, stats, status)."""
+    return _loops2("tm_loops_oet", ("vv", "ws"), ctx, gauge, params, lt, want_raw, check)
+
+
+def tm_loops_hpe(ctx, gauge, params, lt, want_raw=False, check=True):
+    """Standard and hopping-parameter-expansion loops from the same solves:
+    dict(est_std, est_hpe (90, lt) complex (est_hpe NaN beyond the 16 local
+    ops), var_re_std, var_im_std, var_re_hpe, var_im_hpe, optional raw_std_hp,
+    raw_std_lp, raw_hpe_hp, raw_hpe_lp, stats, status)."""
+    return _loops2("tm_loops_hpe", ("std", "hpe"), ctx, gauge, params, lt, want_raw, check)
 
 
 def tm_project_loops(raw: np.ndarray) -> np.ndarray:

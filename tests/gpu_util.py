@@ -52,7 +52,7 @@ def apply_op(g, op, kappa, a, prec, psi, dims):
     hb = fb // 2
     fin = torch.empty(nrhs * fb, dtype=torch.uint8, device="cuda")
     tm.tm_field_import(ctx, g, prec, nrhs, to_dev(psi), fin)
-    full = op in ("hop", "m", "mdag")
+    full = op in ("hop", "m", "mdag", "bh")
     if full:
         fout = torch.zeros_like(fin)
         tm.tm_dslash(ctx, g, op, kappa, a, prec, nrhs, fin, fout)

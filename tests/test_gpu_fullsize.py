@@ -122,3 +122,23 @@ def test_fullsize_loops_oet_f64(oracle, big):
     r = tm.tm_loops_oet(ctx, g, P, DIMS[3], want_raw=True)
     for f in ("vv", "ws"):
         assert GU.relerr(r[f"raw_{f}_lp"][0], ref["raw"]["lp_" + f][0]) < 1e-10, f
+
+
+def test_fullsize_loops_hpe(oracle, big):
+    """Hopping parameter expansion at 32^3x64 (five matched iterations): the
+    FP64 path's eta^dag (BH)^4 s local spin matrices to 1e-10 of the oracle,
+    and the FP16 LP path (12 sources per batch, the bench's launch shape)
+    within its storage rounding, on sampled sources."""
+    from paper_1401_6749_amd import tm
+
+    U, g = big
+    ctx = GU.context()
+    ref = oracle.loops_hpe(DIMS, -1, U, KAPPA, A, 104, 0, 12, lp_fixed_iters=5, source_ids=[0, 11],
+                           return_raw=True)
+    P64 = tm.tsm_params(KAPPA, A, 104, 0, 12, lp=tm.solver_params("f64", fixed_iters=5), batch=12)
+    r64 = tm.tm_loops_hpe(ctx, g, P64, DIMS[3], want_raw=True)
+    P16 = tm.tsm_params(KAPPA, A, 104, 0, 12, lp=tm.solver_params("lp", fixed_iters=5, half="f16"), batch=12)
+    r16 = tm.tm_loops_hpe(ctx, g, P16, DIMS[3], want_raw=True)
+    for j in (0, 11):
+        assert GU.relerr(r64["raw_hpe_lp"][j], ref["raw"]["lp_hpe"][j]) < 1e-10, j
+        assert GU.relerr(r16["raw_hpe_lp"][j], ref["raw"]["lp_hpe"][j]) < 5e-3, j
