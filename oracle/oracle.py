@@ -23,6 +23,9 @@ in NumPy:
   * ``apply_bh`` / ``hpe_exact`` / ``loops_hpe``
                                 the hopping parameter expansion (Sec. 2.4,
                                 Eq. HPE and Eq. loopHPE1).
+  * ``tdil_mask`` / ``tdil_valid`` / ``loops_tdil``
+                                time dilution and coherent sources (Sec. 2.3),
+                                alone or with the expansion.
 
 Array layouts (complex128): spinor (V, 4, 3), gauge (V, 4, 3, 3), with
 lex = x + Lx*(y + Ly*(z + Lz*t)).  ``a`` always means 2*kappa*mu.
@@ -527,5 +530,113 @@ def loops_hpe(dims, tbc, U, kappa, a, noise_seed, n_hp, n_lp, hp_tol=1e-10, lp_t
                 est[N_LOCAL:] = np.nan
                 vre[N_LOCAL:] = np.nan
                 vim[N_LOCAL:] = np.nan
+            res.update({"est_" + f: est, "var_re_" + f: vre, "var_im_" + f: vim})
+    return res
+
+
+# ----------------------------------------------------------------------------
+# Time dilution and coherent sources (Sec. 2.3)
+# ----------------------------------------------------------------------------
+def tdil_mask(dims, spacing, phase):
+    """Sites (V,) bool of the diluted source: timeslices t with t mod spacing
+    == phase.  spacing = T is full time dilution (one timeslice per source);
+    a smaller spacing puts T/spacing coherent timeslices, spacing apart, in one
+    source."""
+    d = _dims(dims)
+    T = int(d[3])
+    if spacing < 1 or T % spacing or not 0 <= phase < spacing:
+        raise ValueError("need 1 <= spacing, T % spacing == 0 and 0 <= phase < spacing")
+    v3 = int(d[0]) * int(d[1]) * int(d[2])
+    t = np.repeat(np.arange(T), v3)
+    return t % spacing == phase
+
+
+def tdil_valid(T, spacing, phases):
+    """(90, T) bool: the (operator, t) entries the diluted estimator covers.
+    The noise must cover the timeslices each contraction reads it on: t for
+    local and spatial-derivative loops; t-1, t and t+1 for L^D_{G,t} (its F(t-1)
+    and B(t) terms) and for the symmetrised operators that contain it."""
+    cov = np.zeros(T, dtype=bool)
+    for p in phases:
+        cov[np.arange(T) % spacing == p] = True
+    wide = cov & np.roll(cov, 1) & np.roll(cov, -1)
+    ok = np.zeros((N_OPS, T), dtype=bool)
+    ok[:N_LOCAL] = cov
+    for g in range(16):
+        for nu in range(4):
+            ok[N_LOCAL + 4 * g + nu] = wide if nu == 3 else cov
+    for i, (m, n) in enumerate(SYM_PAIRS):
+        ok[N_LOCAL + N_DERIV + i] = wide if 3 in (m, n) else cov
+    return ok
+
+
+def loops_tdil(dims, tbc, U, kappa, a, noise_seed, n_hp, n_lp, spacing, phases=None, hpe=False, hp_tol=1e-10,
+               lp_tol=1e-2, max_iter=100000, lp_fixed_iters=0, source_ids=None, return_raw=False):
+    """Time-diluted loops (Sec. 2.3) with the truncated solver method.
+
+    Noise vector r (``z4_source`` id r) is split into the sources
+    eta_{r,p} = eta_r on the timeslices of ``tdil_mask(spacing, p)`` for p in
+    ``phases`` (default: all spacing phases); each is solved (HP and LP for
+    r < n_hp, LP only above), and the loops of noise vector r are the sums over
+    its phases of contract(eta_{r,p}, s_{r,p}): a source contributes to the
+    signal only on its own timeslices.  With ``hpe`` the same is done for the
+    stochastic term of Eq. loopHPE1 (eta_{r,p}^dag G (BH)^4 s_{r,p}) and the
+    exact part is added as in ``loops_hpe``.  TSM over noise vectors as in
+    ``loops_tsm``; entries outside ``tdil_valid`` are NaN.
+    """
+    d = _dims(dims)
+    T = int(d[3])
+    phases = list(range(spacing)) if phases is None else [int(p) for p in phases]
+    masks = {p: tdil_mask(dims, spacing, p) for p in phases}
+    valid = tdil_valid(T, spacing, phases)
+    ids = list(range(n_hp + n_lp)) if source_ids is None else list(source_ids)
+    tags = ("std", "hpe") if hpe else ("std",)
+    raws = {f"{h}_{f}": {} for h in ("hp", "lp") for f in tags}
+
+    def add(tag, j, eta, s):
+        P = contract(dims, tbc, U, eta, s)
+        acc = raws[tag + "_std"]
+        acc[j] = acc.get(j, 0) + P
+        if hpe:
+            w = s
+            for _ in range(4):
+                w = apply_bh(dims, tbc, U, kappa, a, w)
+            Ph = np.zeros_like(P)
+            Ph[0] = contract(dims, tbc, U, eta, w)[0]
+            acch = raws[tag + "_hpe"]
+            acch[j] = acch.get(j, 0) + Ph
+
+    t0 = time.perf_counter()
+    for j in ids:
+        eta_full = z4_source(dims, noise_seed, j)
+        for p in phases:
+            eta = eta_full * masks[p][:, None, None]
+            if j < n_hp:
+                s, _, _, _ = solve(dims, tbc, U, kappa, a, eta, tol=hp_tol, max_iter=max_iter)
+                add("hp", j, eta, s)
+            s, _, _, _ = solve(dims, tbc, U, kappa, a, eta, tol=lp_tol, max_iter=max_iter,
+                               fixed_iters=lp_fixed_iters)
+            add("lp", j, eta, s)
+    loops = {k: {j: project(v) for j, v in r.items()} for k, r in raws.items()}
+    res = {"seconds": time.perf_counter() - t0, "loops": loops, "valid": valid}
+    if return_raw:
+        res["raw"] = raws
+    if source_ids is None:
+        exact_ops = None
+        if hpe:
+            exact_ops = project(np.concatenate([hpe_exact(dims, kappa, a)[None],
+                                                np.zeros((8, T, 4, 4), dtype=np.complex128)]))
+        for f in tags:
+            hp = np.array([loops["hp_" + f][j] for j in range(n_hp)]).reshape(n_hp, N_OPS, T)
+            lpc = np.array([loops["lp_" + f][j] for j in range(n_hp)]).reshape(n_hp, N_OPS, T)
+            lpb = np.array([loops["lp_" + f][j] for j in range(n_hp, n_hp + n_lp)]).reshape(n_lp, N_OPS, T)
+            est, vre, vim = tsm_combine(hp, lpc, lpb)
+            ok = valid.copy()
+            if f == "hpe":
+                est = est + exact_ops
+                ok[N_LOCAL:] = False
+            est[~ok] = np.nan
+            vre[~ok] = np.nan
+            vim[~ok] = np.nan
             res.update({"est_" + f: est, "var_re_" + f: vre, "var_im_" + f: vim})
     return res
