@@ -253,6 +253,119 @@ def hpe_segment(tm, np, ctx, g, W, n_hp=12, n_lp=240):
             "error_ratio_local_range": [float(np.nanmin(ratio)), float(np.nanmax(ratio))]}
 
 
+def tdil_segment(tm, np, ctx, g, W, t_ins=8, n_hp=12, n_lp=240):
+    """Full time dilution at one insertion timeslice (one solve per noise
+    vector on timeslice t_ins, with and without the expansion) against the
+    undiluted estimator with the same number of solves: solves/s of both and,
+    for the 16 local loops at t_ins, the median ratio of standard errors
+    (time-diluted / undiluted, and time-diluted + HPE / undiluted)."""
+    lt = W["dims"][3]
+    P = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"] + 17, n_hp, n_lp, hp=tm.solver_params("mixed", tol=1e-10),
+                      lp=tm.solver_params("lp", tol=1e-2, half=W["half"]), batch=W["batch"])
+    t0 = time.perf_counter()
+    rd = tm.tm_loops_tdil(ctx, g, P, lt, lt, phases=[t_ins], hpe=True)
+    t_dil = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ru = tm.tm_loops_tsm(ctx, g, P, lt)
+    t_und = time.perf_counter() - t0
+    vu = (ru["var_re"] + ru["var_im"])[:16, t_ins]
+    vd = (rd["var_re_std"] + rd["var_im_std"])[:16, t_ins]
+    vh = (rd["var_re_hpe"] + rd["var_im_hpe"])[:16, t_ins]
+    n = 2 * n_hp + n_lp
+    return {"t_ins": t_ins, "noise_vectors": n_hp + n_lp, "solves": n,
+            "tdil_hpe_solves_per_s": round(n / t_dil, 1), "undiluted_solves_per_s": round(n / t_und, 1),
+            "error_ratio_tdil_local_median": float(np.median(np.sqrt(vd / vu))),
+            "error_ratio_tdil_hpe_local_median": float(np.median(np.sqrt(vh / vu))),
+            "covered_local_timeslices": int(np.isfinite(rd["est_std"][0]).sum())}
+
+
+def _tsm_var(np, hp, lpc, lpb):
+    """TSM variance per (op, t) from per-source ops (Eq. estiTSM with sample
+    variances, n - 1): s^2(hp - lpc)/N_HP + s^2(lpb)/N_LP, real + imaginary."""
+    v = np.zeros(hp.shape[1:])
+    if len(hp):
+        d = hp - lpc
+        v = v + (np.var(d.real, axis=0, ddof=1) + np.var(d.imag, axis=0, ddof=1)) / len(hp)
+    if len(lpb):
+        v = v + (np.var(lpb.real, axis=0, ddof=1) + np.var(lpb.imag, axis=0, ddof=1)) / len(lpb)
+    return v
+
+
+def tsm_scan(tm, np, ctx, g, W):
+    """Tuning scan of the truncated solver method (Sec. 2.1, Fig. 1 and
+    Table 1 analogues on the synthetic field):
+      n_lp:        TSM error of the scalar loop and of i psibar g3 D3 psi
+                   against N_LP at fixed N_HP (the error should fall as
+                   N_LP^-1/2 while the correction term is small);
+      truncation:  LP stopping residual against LP iterations and the
+                   efficiency ratio R_C R_E^2 = (T_TSM s^2_TSM)/(T_plain s^2_plain)
+                   (below 1: TSM is favourable), medians over local and
+                   derivative operators and t;
+      mass:        the same ratio against 2 kappa mu at the bench's kappa.
+    The plain estimator is N HP solves (mixed precision to 1e-10)."""
+    lt = W["dims"][3]
+    hp = tm.solver_params("mixed", tol=1e-10)
+    seed = W["noise_seed"] + 31
+    out = {"workload": f"{W['dims'][0]}^3x{lt}", "kappa": W["kappa"]}
+
+    # error against N_LP
+    n_hp, n_lp = 24, 480
+    P = tm.tsm_params(W["kappa"], W["a"], seed, n_hp, n_lp, hp=hp, lp=tm.solver_params("lp", tol=1e-2, half=W["half"]),
+                      batch=W["batch"])
+    r = tm.tm_loops_tsm(ctx, g, P, lt, want_raw=True)
+    raw = r["raw"][..., 0] + 1j * r["raw"][..., 1]
+    ops = tm.tm_project_loops(raw)
+    hp_ops, lp_ops = ops[:n_hp], ops[n_hp:]
+    d3 = 16 + 4 * 3 + 2  # i psibar gamma_3 D_3 psi: insertion gamma_3 (index 3), direction z
+    rows = []
+    for n in (30, 60, 120, 240, 480):
+        v = _tsm_var(np, hp_ops, lp_ops[:n_hp], lp_ops[n_hp:n_hp + n])
+        vc = _tsm_var(np, hp_ops, lp_ops[:n_hp], lp_ops[:0])
+        rows.append({"n_lp": n, "sigma_scalar": float(np.median(np.sqrt(v[0]))),
+                     "sigma_g3D3": float(np.median(np.sqrt(v[d3]))),
+                     "correction_share_scalar": float(np.median(vc[0] / v[0]))})
+    ln = np.log([x["n_lp"] for x in rows])
+    out["n_lp"] = {"n_hp": n_hp, "rows": rows,
+                   "slope_scalar": float(np.polyfit(ln, np.log([x["sigma_scalar"] for x in rows]), 1)[0]),
+                   "slope_g3D3": float(np.polyfit(ln, np.log([x["sigma_g3D3"] for x in rows]), 1)[0])}
+
+    def plain(a, n=24):
+        Pp = tm.tsm_params(W["kappa"], a, seed + 1, 0, n, lp=hp, batch=W["batch"])
+        t0 = time.perf_counter()
+        rp = tm.tm_loops_tsm(ctx, g, Pp, lt)
+        return time.perf_counter() - t0, rp["var_re"] + rp["var_im"], rp["stats"]["lp_iters"] / n
+
+    def tsm(a, tol, n_hp=12, n_lp=120):
+        Pt = tm.tsm_params(W["kappa"], a, seed + 2, n_hp, n_lp, hp=hp,
+                           lp=tm.solver_params("lp", tol=tol, half=W["half"]), batch=W["batch"])
+        t0 = time.perf_counter()
+        rt = tm.tm_loops_tsm(ctx, g, Pt, lt)
+        st = rt["stats"]
+        return (time.perf_counter() - t0, rt["var_re"] + rt["var_im"], st["lp_iters"] / max(1, st["lp_solves"]),
+                st["hp_iters"] / max(1, st["hp_solves"]))
+
+    def ratio(tp, vp, tt, vt):
+        q = (tt * vt) / (tp * vp)
+        return float(np.median(q[:16])), float(np.median(q[16:80]))
+
+    tp, vp, _ = plain(W["a"])
+    rows = []
+    for tol in (3e-1, 1e-1, 3e-2, 1e-2, 3e-3, 1e-3):
+        tt, vt, it_lp, _ = tsm(W["a"], tol)
+        loc, der = ratio(tp, vp, tt, vt)
+        rows.append({"lp_tol": tol, "lp_iters": it_lp, "rc_re2_local": loc, "rc_re2_deriv": der})
+    out["truncation"] = rows
+    rows = []
+    for a in (0.0033, 0.01, 0.03, 0.1):
+        tp, vp, it_hp_plain = plain(a)
+        tt, vt, it_lp, it_hp = tsm(a, 1e-2)
+        loc, der = ratio(tp, vp, tt, vt)
+        rows.append({"two_kappa_mu": a, "hp_iters": it_hp, "lp_iters": it_lp, "rc_re2_local": loc,
+                     "rc_re2_deriv": der})
+    out["mass"] = rows
+    return out
+
+
 def r_hp_lp(tm, ctx, g, W, n=12):
     """R_HP/LP: GPU time of n HP sources (solve + contraction) over that of n LP
     sources, from one run with n LP-only sources and one with n HP sources (each
@@ -364,6 +477,8 @@ def main():
                     help="skip the precision, R_HP/LP and serving segments")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the copy calibration and the roofline kernel (for counter runs)")
+    ap.add_argument("--scan", metavar="OUT_JSON",
+                    help="run the TSM tuning scan (after one warm-up step), write it to OUT_JSON and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the roofline kernel's HBM traffic from two rocprofv3 --pmc databases "
                          "(FETCH_SIZE, WRITE_SIZE) of --roofline-only runs and exit")
@@ -405,6 +520,16 @@ def main():
     for i in range(args.warmup):
         r = tm.tm_loops_tsm(ctx, g, P, lt)
         log(f"warmup step {i} {r['stats']['seconds']:.2f}s")
+    if args.scan:
+        t1 = time.perf_counter()
+        scan = tsm_scan(tm, np, ctx, g, W)
+        scan["command"] = f"python3 bench.py --scan {args.scan}"
+        scan["seconds"] = round(time.perf_counter() - t1, 1)
+        with open(args.scan, "w") as f:
+            json.dump(scan, f, indent=1)
+            f.write("\n")
+        print(json.dumps(scan), flush=True)
+        return
     if args.serving_only:
         rate = n_src / r["stats"]["seconds"]
         print(json.dumps({"serving": serving_segment(tm, np, inputs, ctx, g, W, rate, args.serve_requests)}),
@@ -454,7 +579,7 @@ def main():
 
     roofline = measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)
 
-    precision = rhl = serving = oet = hpe = None
+    precision = rhl = serving = oet = hpe = tdil = None
     if not args.no_extra:
         t0 = time.perf_counter()
         precision = precision_segment(tm, np, ctx, g, W)
@@ -465,6 +590,9 @@ def main():
         hpe = hpe_segment(tm, np, ctx, g, W)
         log(f"HPE: {hpe['hpe_sources_per_s']} sources/s vs {hpe['standard_sources_per_s']}; "
             f"local error ratio {hpe['error_ratio_local_median']:.2f}")
+        tdil = tdil_segment(tm, np, ctx, g, W)
+        log(f"time dilution at t={tdil['t_ins']}: error ratio {tdil['error_ratio_tdil_local_median']:.2f}, "
+            f"with HPE {tdil['error_ratio_tdil_hpe_local_median']:.2f} at equal solves")
         log(f"precision and R_HP/LP segments in {time.perf_counter() - t0:.1f}s; R_HP/LP {rhl['value']}")
         if args.serve_requests > 0:
             serving = serving_segment(tm, np, inputs, ctx, g, W, value, args.serve_requests)
@@ -530,6 +658,7 @@ def main():
         "r_hp_lp": rhl,
         "one_end_trick": oet,
         "hpe": hpe,
+        "time_dilution": tdil,
         "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,

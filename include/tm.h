@@ -309,6 +309,34 @@ int tm_loops_oet(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *pa
 int tm_loops_hpe(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *params, double *est,
                  double *var_re, double *var_im, double *raw, tm_tsm_stats *stats);
 
+/* Time dilution and coherent sources (Sec. 2.3), optionally with the
+ * hopping parameter expansion.  Noise vector r (ids and TSM sets as in
+ * tm_loops_tsm) is split into one source per phase p: eta_r on the
+ * timeslices t with t mod spacing == p (spacing = Lt: full time dilution;
+ * smaller spacing: coherent sources with Lt/spacing timeslices, spacing
+ * apart).  Every such source is solved (HP and LP in the correction set, LP
+ * in the bulk), contracted, and the spin matrices of noise vector r are the
+ * sums over its phases in phase order; the TSM combination then runs over
+ * noise vectors.
+ *   spacing:  divides Lt;
+ *   phases:   n_phases distinct values in [0, spacing) (host), or NULL for
+ *             all spacing phases; the cost is n_phases solves per noise
+ *             vector and solver;
+ *   hpe:      0: one estimator (flavour 0, as tm_loops_tsm); 1: also the
+ *             expansion (flavour 1, as tm_loops_hpe, every extent >= 4).
+ * Covered entries: a loop at t needs the noise on t (local and
+ * spatial-derivative operators) or on t - 1, t and t + 1 (the time
+ * derivative and the symmetrised operators containing it); est and the
+ * variances are NaN elsewhere, and for ops 16..89 of flavour 1.
+ * Outputs: est [1 + hpe][TM_N_OPS][Lt][2], var_re/var_im [1 + hpe][TM_N_OPS][Lt],
+ * raw (optional) [1 + hpe][n_hp + n_hp + n_lp][9][Lt][4][4][2] per noise
+ * vector (summed over its phases).  Device memory grows with
+ * n_phases x (2 n_hp + n_lp) spin-matrix sets of 9 Lt 32 doubles each.
+ * Errors: TM_ERR_ARG (spacing, phases, extents), then as tm_loops_tsm. */
+int tm_loops_tdil(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *params, int spacing,
+                  const int *phases, int n_phases, int hpe, double *est, double *var_re, double *var_im, double *raw,
+                  tm_tsm_stats *stats);
+
 /* Project spin matrices [n][9][Lt][4][4][2] (host) onto the 90 operator
  * loops [n][TM_N_OPS][Lt][2] (host), as in tm_loops_tsm. */
 int tm_project_loops(int n, int lt, const double *raw, double *ops);

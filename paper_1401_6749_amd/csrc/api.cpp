@@ -624,8 +624,14 @@ extern "C" int tm_project_loops(int n, int lt, const double *raw, double *ops)
 // estimators of tsm_run: eta^dag G s; the one-end trick (isovector, isoscalar);
 // eta^dag G s and the hopping parameter expansion from the same solves
 enum Est { EST_STD = 0, EST_OET = 1, EST_HPE = 2 };
+// time dilution (Sec. 2.3): noise vector r becomes one source per phase p,
+// eta_r on the timeslices t = p mod spacing; spacing 0 = undiluted
+struct Dil {
+    int spacing = 0;
+    std::vector<int> phases;
+};
 int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *vre, double *vim,
-            double *raw_host, tm_tsm_stats *stats, Est mode = EST_STD);
+            double *raw_host, tm_tsm_stats *stats, Est mode = EST_STD, const Dil &dil = Dil());
 
 extern "C" int tm_loops_tsm(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *var_re,
                             double *var_im, double *raw, tm_tsm_stats *stats)
@@ -650,6 +656,40 @@ extern "C" int tm_loops_hpe(tm_context *ctx, const tm_gauge *G, const tm_tsm_par
             if (G->dims[d] < 4)
                 return set_err(ctx, TM_ERR_ARG, "tm_loops_hpe: every extent must be >= 4 (got %d)", G->dims[d]);
     return tsm_run(ctx, G, P, est, var_re, var_im, raw, stats, EST_HPE);
+}
+
+extern "C" int tm_loops_tdil(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, int spacing,
+                             const int *phases, int n_phases, int hpe, double *est, double *var_re, double *var_im,
+                             double *raw, tm_tsm_stats *stats)
+{
+    if (!ctx) return TM_ERR_ARG;
+    if (!G || !P || G->ctx != ctx) return set_err(ctx, TM_ERR_ARG, "tm_loops_tdil: null gauge/parameters or another context's gauge");
+    const int lt = G->dims[3];
+    if (spacing < 1 || spacing > lt || lt % spacing)
+        return set_err(ctx, TM_ERR_ARG, "tm_loops_tdil: spacing must divide the time extent %d (got %d)", lt, spacing);
+    Dil dil;
+    dil.spacing = spacing;
+    if (!phases) {
+        for (int p = 0; p < spacing; p++) dil.phases.push_back(p);
+    } else {
+        if (n_phases < 1 || n_phases > spacing) return set_err(ctx, TM_ERR_ARG, "tm_loops_tdil: need 1..spacing phases");
+        std::vector<char> seen(spacing, 0);
+        for (int k = 0; k < n_phases; k++) {
+            const int p = phases[k];
+            if (p < 0 || p >= spacing || seen[p])
+                return set_err(ctx, TM_ERR_ARG, "tm_loops_tdil: phases must be distinct and in [0, spacing)");
+            seen[p] = 1;
+            dil.phases.push_back(p);
+        }
+    }
+    if ((size_t)(2 * P->n_hp + P->n_lp) * dil.phases.size() > (size_t)1 << 26)
+        return set_err(ctx, TM_ERR_ARG, "tm_loops_tdil: too many solves");
+    if (hpe)
+        for (int d = 0; d < 4; d++)
+            if (G->dims[d] < 4)
+                return set_err(ctx, TM_ERR_ARG, "tm_loops_tdil: the expansion needs every extent >= 4 (got %d)",
+                               G->dims[d]);
+    return tsm_run(ctx, G, P, est, var_re, var_im, raw, stats, hpe ? EST_HPE : EST_STD, dil);
 }
 
 // insertion tables of the one-end trick: g5 G (flavour 0) and g5 G g5 (flavour 1),
@@ -680,8 +720,34 @@ int tsm_check(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P)
     return TM_OK;
 }
 
+// (operator, t) entries an estimator covers: with time dilution, local and
+// spatial-derivative loops need the noise on t, the time-derivative loops
+// (and the symmetrised operators containing one) on t - 1, t and t + 1; the
+// expansion covers the 16 local loops only
+static void valid_mask(int lt, const Dil &dil, bool local_only, unsigned char *m)
+{
+    std::vector<unsigned char> cov(lt, 1), wide(lt, 1);
+    if (dil.spacing > 0)
+        for (int t = 0; t < lt; t++) {
+            cov[t] = 0;
+            for (int p : dil.phases) cov[t] |= (unsigned char)(t % dil.spacing == p);
+        }
+    for (int t = 0; t < lt; t++) wide[t] = cov[t] && cov[(t + 1) % lt] && cov[(t + lt - 1) % lt];
+    for (int op = 0; op < TM_N_OPS; op++) {
+        bool tder = false;
+        if (op >= 16 && op < 80) tder = (op - 16) % 4 == 3;
+        if (op >= 80) {
+            int i = op - 80, m = 0;
+            while (i >= 4 - m) i -= 4 - m++;
+            tder = m == 3 || m + i == 3;
+        }
+        for (int t = 0; t < lt; t++)
+            m[op * lt + t] = (local_only && op >= 16) ? 0 : tder ? wide[t] : cov[t];
+    }
+}
+
 int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *est, double *vre, double *vim,
-            double *raw_host, tm_tsm_stats *stats, Est mode)
+            double *raw_host, tm_tsm_stats *stats, Est mode, const Dil &dil)
 {
     const bool oet = mode == EST_OET, hpe = mode == EST_HPE;
     if (!est || !vre || !vim) return set_err(ctx, TM_ERR_ARG, "tm_loops: null output");
@@ -697,8 +763,15 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
     const int nf = mode == EST_STD ? 1 : 2;
     const size_t raw_per = (size_t)9 * lt * 32;  // doubles per source
     const size_t ops_per = (size_t)TM_N_OPS * lt * 2;
-    const size_t src_raw = (size_t)(n_hp + n_lpt) * raw_per, src_ops = (size_t)(n_hp + n_lpt) * ops_per;
-    const size_t dev_doubles = nf * (src_raw + src_ops + ops_per * 2) + (hpe ? raw_per + ops_per : 0);
+    const size_t n_ids = (size_t)(n_hp + n_lpt);
+    const size_t src_raw = n_ids * raw_per, src_ops = n_ids * ops_per;
+    // with more than one phase each solve has its own spin matrices, summed
+    // per noise vector in phase order afterwards
+    const int nph = dil.spacing > 0 ? (int)dil.phases.size() : 1;
+    const size_t job_raw = nph > 1 ? n_ids * nph * raw_per : 0;  // per flavour
+    const size_t mask_doubles = ((size_t)nf * TM_N_OPS * lt + 7) / 8;
+    const size_t dev_doubles =
+        nf * (src_raw + job_raw + src_ops + ops_per * 2) + (hpe ? raw_per + ops_per : 0) + mask_doubles;
     double *dbuf = (double *)dalloc(ctx, dev_doubles * sizeof(double));
     if (!dbuf) return set_err(ctx, TM_ERR_NOMEM, "tm_loops: no memory for per-source loops");
     // the expansion's raw spin matrices carry the local kind only
@@ -713,41 +786,45 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
     // flavour f: raw [n_hp | n_lpt] sources, ops likewise, then est and variances
     auto raw_hp = [&](int f) { return dbuf + f * src_raw; };
     auto raw_lp = [&](int f) { return raw_hp(f) + n_hp * raw_per; };
-    double *opsb = dbuf + nf * src_raw;
+    double *jobb = dbuf + nf * src_raw;
+    // spin matrices of the solve of noise vector i (HP, or LP), phase k
+    auto job_out = [&](int f, bool is_hp, int i, int k) {
+        if (nph == 1) return (is_hp ? raw_hp(f) : raw_lp(f)) + (size_t)i * raw_per;
+        return jobb + f * job_raw + ((is_hp ? 0 : (size_t)n_hp) + i) * nph * raw_per + (size_t)k * raw_per;
+    };
+    double *opsb = jobb + nf * job_raw;
     auto ops_hp = [&](int f) { return opsb + f * src_ops; };
     auto ops_lp = [&](int f) { return ops_hp(f) + n_hp * ops_per; };
     double *estb = opsb + nf * src_ops;
     auto d_est = [&](int f) { return estb + f * 2 * ops_per; };
     double *raw_exact = estb + nf * 2 * ops_per, *ops_exact = raw_exact + raw_per;  // HPE only
-    std::vector<Job> hp(n_hp), lp(n_lpt);
+    unsigned char *d_mask = (unsigned char *)(estb + nf * 2 * ops_per + (hpe ? raw_per + ops_per : 0));
+    std::vector<Job> hp((size_t)n_hp * nph), lp((size_t)n_lpt * nph);
     std::vector<Job *> qh, ql;
-    for (int i = 0; i < n_hp; i++) {
-        Job &j = hp[i];
+    auto make = [&](Job &j, bool is_hp, int i, int k) {
         j.noise = true;
         j.seed = P->noise_seed;
         j.src = i;
-        job_from(j, P->hp, P->kappa, P->two_kappa_mu);
-        j.raw_out = raw_hp(0) + i * raw_per;
+        j.tmod = dil.spacing;
+        j.tph = dil.spacing > 0 ? dil.phases[k] : 0;
+        job_from(j, is_hp ? P->hp : P->lp, P->kappa, P->two_kappa_mu);
+        j.raw_out = job_out(0, is_hp, i, k);
         j.oet = oet;
         j.hpe = hpe;
-        j.raw_out2 = nf > 1 ? raw_hp(1) + i * raw_per : nullptr;
+        j.raw_out2 = nf > 1 ? job_out(1, is_hp, i, k) : nullptr;
         j.want_true = P->want_true_resid;
-        j.hp = true;
-        qh.push_back(&j);
-    }
-    for (int i = 0; i < n_lpt; i++) {
-        Job &j = lp[i];
-        j.noise = true;
-        j.seed = P->noise_seed;
-        j.src = i;
-        job_from(j, P->lp, P->kappa, P->two_kappa_mu);
-        j.raw_out = raw_lp(0) + i * raw_per;
-        j.oet = oet;
-        j.hpe = hpe;
-        j.raw_out2 = nf > 1 ? raw_lp(1) + i * raw_per : nullptr;
-        j.want_true = P->want_true_resid;
-        ql.push_back(&j);
-    }
+        j.hp = is_hp;
+    };
+    for (int i = 0; i < n_hp; i++)
+        for (int k = 0; k < nph; k++) {
+            make(hp[(size_t)i * nph + k], true, i, k);
+            qh.push_back(&hp[(size_t)i * nph + k]);
+        }
+    for (int i = 0; i < n_lpt; i++)
+        for (int k = 0; k < nph; k++) {
+            make(lp[(size_t)i * nph + k], false, i, k);
+            ql.push_back(&lp[(size_t)i * nph + k]);
+        }
     std::vector<Batch *> bs;
     std::vector<std::vector<Job *>> qs;
     std::vector<hipStream_t> streams;
@@ -772,6 +849,7 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         batch_destroy(B);
     }
     hipStream_t s = streams.empty() ? nullptr : streams.back();
+    std::vector<unsigned char> mask;  // host source of an async copy: outlives the stream syncs below
     if (!rc) {
         for (hipStream_t x : streams) hipStreamSynchronize(x);
         int tv[64], tw[64];
@@ -780,8 +858,20 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
             launch_hpe_exact(G->g, P->kappa, P->two_kappa_mu, raw_exact, s);
             launch_project(1, lt, raw_exact, ops_exact, gamma_table(), s);
         }
-        hipError_t e = hipSuccess;
+        // covered entries per flavour (the rest NaN); masks only where some entry is not covered
+        mask.assign((size_t)nf * TM_N_OPS * lt, 0);
+        bool masked[2] = {false, false};
+        for (int f = 0; f < nf; f++) {
+            unsigned char *m = mask.data() + (size_t)f * TM_N_OPS * lt;
+            valid_mask(lt, dil, hpe && f == 1, m);
+            for (size_t q = 0; q < (size_t)TM_N_OPS * lt; q++) masked[f] |= m[q] == 0;
+        }
+        hipError_t e = hipMemcpyAsync(d_mask, mask.data(), mask.size(), hipMemcpyHostToDevice, s);
         for (int f = 0; f < nf && e == hipSuccess; f++) {
+            if (nph > 1) {
+                launch_sum_phases(job_out(f, true, 0, 0), raw_hp(f), n_hp, nph, raw_per, s);
+                launch_sum_phases(job_out(f, false, 0, 0), raw_lp(f), n_lpt, nph, raw_per, s);
+            }
             const int *gt = !oet ? gamma_table() : f == 0 ? tv : tw;
             double *de = d_est(f), *dvre = de + ops_per, *dvim = dvre + ops_per / 2;
             launch_project(n_hp, lt, raw_hp(f), ops_hp(f), gt, s);
@@ -789,7 +879,8 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
             // HPE flavour: exact part added to the 16 local loops, the others undefined
             const bool hf = hpe && f == 1;
             launch_tsm_combine(n_hp, P->n_lp, lt, ops_hp(f), ops_lp(f), ops_lp(f) + (size_t)n_hp * ops_per, de, dvre,
-                               dvim, s, hf ? ops_exact : nullptr, hf ? 16 : 90);
+                               dvim, s, hf ? ops_exact : nullptr,
+                               masked[f] ? d_mask + (size_t)f * TM_N_OPS * lt : nullptr);
             e = hipMemcpyAsync(est + f * ops_per, de, ops_per * sizeof(double), hipMemcpyDeviceToHost, s);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(vre + f * ops_per / 2, dvre, ops_per / 2 * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -809,9 +900,11 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
     dfree(ctx, dbuf);
     const double t1 = now_s();
     int worst = TM_OK;
+    const Job *bad = nullptr;  // first solve that ended with non-finite values
     if (stats) std::memset(stats, 0, sizeof(*stats));
     for (auto *v : {&hp, &lp})
         for (Job &j : *v) {
+            if (j.status == TM_ERR_NUMERIC && !bad) bad = &j;
             if (stats) {
                 if (j.hp) {
                     stats->hp_solves++;
@@ -835,7 +928,12 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         stats->lp_seconds = lp_end > 0 ? lp_end - t0 : 0;
     }
     if (rc) return rc;
-    if (worst == TM_ERR_NUMERIC) return set_err(ctx, worst, "tm_loops: non-finite values in a solve");
+    if (worst == TM_ERR_NUMERIC)
+        return set_err(ctx, worst,
+                       "tm_loops: non-finite values in a solve (%s source %llu, phase %d: iteration %d, |r|^2 %.3e "
+                       "-> %.3e, pAp %.3e, alpha %.3e, beta %.3e)",
+                       bad->hp ? "HP" : "LP", (unsigned long long)bad->src, bad->tph, bad->end.iter, bad->end.rr,
+                       bad->end.rr_new, bad->end.pap, bad->end.alpha, bad->end.beta);
     if (worst == TM_ERR_NOCONV) return set_err(ctx, worst, "tm_loops: a solve reached max_iter");
     return TM_OK;
 }

@@ -364,6 +364,8 @@ static void fill_noise_run(Batch *b, int s0, int n, Job *const *jobs, int pp)
         job_start(b, s0 + i, j);
         Z.seed[i] = j->seed;
         Z.src[i] = j->src;
+        Z.tmod[i] = j->tmod;
+        Z.tph[i] = j->tph;
         P.kappa[i] = j->kappa;
         P.a[i] = j->a;
         P.tol2[i] = j->fixed > 0 ? 0.0 : j->tol * j->tol;
@@ -621,6 +623,7 @@ static int harvest_done(Batch *b, int slot, const SlotState &S)
 {
     Job *j = b->slot_job[slot];
     j->iters = S.iter;
+    j->end = S;
     j->updates = b->slot_updates[slot];
     j->cg_rel = S.rr0 > 0 ? std::sqrt(std::max(S.status == ST_CONVERGED || S.status == ST_MAXITER ? S.rr : S.rr_new, 0.0) / S.rr0) : 0.0;
     j->status = S.status == ST_CONVERGED ? TM_OK

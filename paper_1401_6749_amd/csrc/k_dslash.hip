@@ -164,7 +164,7 @@ struct RawZ4 {
     }
     __device__ __forceinline__ cpx<T> get(int k) const
     {
-        const T h = (T)0.70710678118654752440;
+        const T h = (code & Z4_ZERO) ? (T)0 : (T)0.70710678118654752440;
         const cpx<T> e{((code >> (2 * k)) & 1u) ? -h : h, ((code >> (2 * k + 1)) & 1u) ? -h : h};
         return cmul(c[k / 6], e);
     }
@@ -480,7 +480,7 @@ __device__ __forceinline__ double epilogue(const DslashArgs &A, int slot, int cb
         cpx<T> y[12];
         if constexpr (SRC & 2) {
             const uint32_t c = A.codes[(size_t)slot * A.codes_slot / 4 + (size_t)A.out_par * vh + cb];
-            const T h = (T)0.70710678118654752440;
+            const T h = (c & Z4_ZERO) ? (T)0 : (T)0.70710678118654752440;
 #pragma unroll
             for (int k = 0; k < 12; k++)
                 y[k] = cpx<T>{((c >> (2 * k)) & 1u) ? -h : h, ((c >> (2 * k + 1)) & 1u) ? -h : h};

@@ -29,7 +29,10 @@ __global__ __launch_bounds__(BLOCK) void k_z4_codes_n(Geom g, Z4Sources Z, uint3
     const int par = blockIdx.y & 1, i = blockIdx.y >> 1;
     if (cb >= g.vh) return;
     const Site s = site_of(g, cb, par);
-    codes[((size_t)i * 2 + par) * g.vh + cb] = z4_code(lex_of(g, s), Z.src[i], Z.seed[i]);
+    uint32_t c = z4_code(lex_of(g, s), Z.src[i], Z.seed[i]);
+    // time dilution: the source lives on the timeslices t = tph mod tmod only
+    if (Z.tmod[i] > 0 && s.t % Z.tmod[i] != Z.tph[i]) c |= Z4_ZERO;
+    codes[((size_t)i * 2 + par) * g.vh + cb] = c;
 }
 
 void launch_z4_codes(const Geom &g, const Z4Sources &Z, int n, uint32_t *codes, hipStream_t s)
@@ -488,11 +491,11 @@ __device__ __forceinline__ void mean_var(int n, const double *a, const double *b
 }
 
 __global__ void k_tsm(int n_hp, int n_lp, int lt, const double *hp, const double *lpc, const double *lpb,
-                      double *est, double *vre, double *vim, const double *add, int nvalid)
+                      double *est, double *vre, double *vim, const double *add, const unsigned char *valid)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;  // over 90 * lt
     if (i >= 90 * lt) return;
-    if (i >= nvalid * lt) {
+    if (valid && !valid[i]) {
         est[2 * i] = est[2 * i + 1] = vre[i] = vim[i] = __builtin_nan("");
         return;
     }
@@ -508,11 +511,33 @@ __global__ void k_tsm(int n_hp, int n_lp, int lt, const double *hp, const double
 
 void launch_tsm_combine(int n_hp, int n_lp, int lt, const double *ops_hp, const double *ops_lp_corr,
                         const double *ops_lp_bulk, double *est, double *var_re, double *var_im, hipStream_t s,
-                        const double *ops_add, int nvalid)
+                        const double *ops_add, const unsigned char *valid)
 {
     const int n = 90 * lt;
     hipLaunchKernelGGL(k_tsm, dim3((n + 127) / 128), dim3(128), 0, s, n_hp, n_lp, lt, ops_hp, ops_lp_corr,
-                       ops_lp_bulk, est, var_re, var_im, ops_add, nvalid);
+                       ops_lp_bulk, est, var_re, var_im, ops_add, valid);
+}
+
+// out[i] = sum over k < nph, in order, of in[i * nph + k] (per elements of per doubles)
+__global__ void k_sum_phases(const double *in, double *out, int n, int nph, size_t per)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (e >= per || i >= n) return;
+    const double *p = in + (size_t)i * nph * per + e;
+    double v = 0.0;
+    for (int k = 0; k < nph; k++) v += p[(size_t)k * per];
+    out[(size_t)i * per + e] = v;
+}
+
+void launch_sum_phases(const double *in, double *out, int n, int nph, size_t per, hipStream_t s)
+{
+    // at most 65535 noise vectors per launch (grid y)
+    for (int i0 = 0; i0 < n; i0 += 65535) {
+        const int m = n - i0 < 65535 ? n - i0 : 65535;
+        hipLaunchKernelGGL(k_sum_phases, dim3((unsigned)((per + 255) / 256), m), dim3(256), 0, s,
+                           in + (size_t)i0 * nph * per, out + (size_t)i0 * per, m, nph, per);
+    }
 }
 
 }  // namespace tmk

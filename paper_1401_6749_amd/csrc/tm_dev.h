@@ -247,6 +247,12 @@ struct SpinorHalfIO {
         float mx = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; k++) mx = fmaxf(mx, fmaxf(fabsf((float)v[k].re), fabsf((float)v[k].im)));
+        // A site whose largest component is below the smallest normal FP32
+        // number is stored as zero: 1/mx would overflow.  Such sites arise in
+        // the tails of fields with exact zeros (time-diluted sources), where
+        // rounding in half storage leaves residues of the spin projections
+        // that shrink by orders of magnitude per Dslash application.
+        if (!(mx >= 1.17549435e-38f)) mx = 0.f;
         const float inv = mx > 0.f ? 1.0f / mx : 0.f;
 #pragma unroll
         for (int g = 0; g < 3; g++) {
@@ -399,11 +405,17 @@ __device__ __forceinline__ uint32_t z4_code(uint64_t lex, uint64_t src, uint64_t
     return (uint32_t)(philox_w0(lex, src, 0, 0, seed, 0) & 0xFFFFFFull);
 }
 
-// unscaled eta component k: (+-1, +-1); multiply by 2^-1/2 for the value
+// A code with this bit set is a site where the source is zero (a time-diluted
+// source outside its timeslices); the 24 noise bits are kept.
+constexpr uint32_t Z4_ZERO = 0x80000000u;
+
+// unscaled eta component k: (+-1, +-1), or 0 at a zero site; multiply by
+// 2^-1/2 for the value
 template <class T>
 __device__ __forceinline__ cpx<T> z4_unscaled(uint32_t code, int k)
 {
-    return cpx<T>{((code >> (2 * k)) & 1u) ? (T)-1 : (T)1, ((code >> (2 * k + 1)) & 1u) ? (T)-1 : (T)1};
+    const T u = (code & Z4_ZERO) ? (T)0 : (T)1;
+    return cpx<T>{((code >> (2 * k)) & 1u) ? -u : u, ((code >> (2 * k + 1)) & 1u) ? -u : u};
 }
 
 // ---------------------------------------------------------------------------

@@ -82,11 +82,13 @@ struct Job {
     bool oet = false;           // one-end trick estimators instead of eta^dag G s
     double *raw_out2 = nullptr; // one-end trick: the isoscalar part; HPE: eta^dag G (BH)^4 s (kind 0) [9][T][16][2]
     bool hpe = false;           // also the stochastic term of the hopping parameter expansion
+    int tmod = 0, tph = 0;      // time dilution: eta only on the timeslices t = tph mod tmod (tmod 0: all)
     int want_true = 0;
     // output
     int status = 0;  // tm_status
     int iters = 0, updates = 0;
     double cg_rel = 0, true_rel = -1;
+    tmk::SlotState end{};  // slot state at the end of the solve (diagnostics)
     double t_fill = 0, t_done = 0;
     // owner bookkeeping
     void *owner = nullptr;

@@ -54,9 +54,11 @@ void launch_site_diag(const Geom &g, int mode, double a, const char *in, char *o
 // ---- noise ----
 // Z4 codes of both parities: codes[par*vh + cb]
 void launch_z4_codes(const Geom &g, uint64_t seed, uint64_t src, uint32_t *codes, hipStream_t s);
-// the same for n sources (n <= MAX_SLOTS) into codes + i * 2 * vh
+// the same for n sources (n <= MAX_SLOTS) into codes + i * 2 * vh; source i
+// is zero outside the timeslices t = tph[i] mod tmod[i] when tmod[i] > 0
 struct Z4Sources {
     uint64_t seed[MAX_SLOTS], src[MAX_SLOTS];
+    int tmod[MAX_SLOTS], tph[MAX_SLOTS];
 };
 void launch_z4_codes(const Geom &g, const Z4Sources &Z, int n, uint32_t *codes, hipStream_t s);
 // eta of one parity as an FP64 half field (times A^-1 when ainv != 0)
@@ -94,11 +96,13 @@ void launch_contract_local(int sps, const Geom &g, const char *s_even, const cha
 void launch_hpe_exact(const Geom &g, double kappa, double a, double *raw, hipStream_t s);
 // raw [n][9][T][16][2] -> ops [n][90][T][2]; gtab: [16][4] (col | phase << 2)
 void launch_project(int n, int lt, const double *raw, double *ops, const int *gtab_host, hipStream_t s);
-// TSM combination over per-source ops; est += ops_add when given; ops from
-// nvalid on are NaN (estimate and variances)
+// TSM combination over per-source ops; est += ops_add when given; entries
+// (op, t) with valid[op * T + t] == 0 are NaN (estimate and variances)
 void launch_tsm_combine(int n_hp, int n_lp, int lt, const double *ops_hp, const double *ops_lp_corr,
                         const double *ops_lp_bulk, double *est, double *var_re, double *var_im, hipStream_t s,
-                        const double *ops_add = nullptr, int nvalid = 90);
+                        const double *ops_add = nullptr, const unsigned char *valid = nullptr);
+// out[i] = sum_k in[i * nph + k] in order k = 0..nph-1, i < n, per doubles each
+void launch_sum_phases(const double *in, double *out, int n, int nph, size_t per, hipStream_t s);
 
 // ---- layout ----
 // canonical FP64 gauge (device) -> per-precision link arrays

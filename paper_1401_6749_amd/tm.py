@@ -120,6 +120,8 @@ _sig = {
                              c_void_p, ctypes.POINTER(tm_tsm_stats)]),
     "tm_loops_hpe": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_void_p, c_void_p, c_void_p,
                              c_void_p, ctypes.POINTER(tm_tsm_stats)]),
+    "tm_loops_tdil": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_int, c_void_p, c_int, c_int,
+                              c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(tm_tsm_stats)]),
     "tm_project_loops": (c_int, [c_int, c_int, c_void_p, c_void_p]),
     "tm_serve_create": (c_int, [c_void_p, c_int, c_size_t, ctypes.POINTER(c_void_p)]),
     "tm_serve_submit": (c_int, [c_void_p, ctypes.POINTER(tm_request)]),
@@ -323,15 +325,16 @@ def tm_loops_tsm(ctx, gauge, params, lt, want_raw=False, check=True):
     return out
 
 
-def _loops2(fn, names, ctx, gauge, params, lt, want_raw, check):
-    est = np.zeros((2, N_OPS, lt, 2))
-    vre = np.zeros((2, N_OPS, lt))
-    vim = np.zeros((2, N_OPS, lt))
+def _loops2(fn, names, ctx, gauge, params, lt, want_raw, check, extra=()):
+    nf = len(names)
+    est = np.zeros((nf, N_OPS, lt, 2))
+    vre = np.zeros((nf, N_OPS, lt))
+    vim = np.zeros((nf, N_OPS, lt))
     n_raw = params.n_hp + params.n_hp + params.n_lp
-    raw = np.zeros((2, n_raw, 9, lt, 4, 4, 2)) if want_raw else None
+    raw = np.zeros((nf, n_raw, 9, lt, 4, 4, 2)) if want_raw else None
     st = tm_tsm_stats()
-    rc = getattr(_lib, fn)(ctx, gauge, ctypes.byref(params), est.ctypes.data, vre.ctypes.data, vim.ctypes.data,
-                           raw.ctypes.data if want_raw else None, ctypes.byref(st))
+    rc = getattr(_lib, fn)(ctx, gauge, ctypes.byref(params), *extra, est.ctypes.data, vre.ctypes.data,
+                           vim.ctypes.data, raw.ctypes.data if want_raw else None, ctypes.byref(st))
     if check:
         _check(ctx, rc, fn)
     out = dict(stats=_stats_dict(st), status=rc)
@@ -358,6 +361,18 @@ def tm_loops_hpe(ctx, gauge, params, lt, want_raw=False, check=True):
     ops), var_re_std, var_im_std, var_re_hpe, var_im_hpe, optional raw_std_hp,
     raw_std_lp, raw_hpe_hp, raw_hpe_lp, stats, status)."""
     return _loops2("tm_loops_hpe", ("std", "hpe"), ctx, gauge, params, lt, want_raw, check)
+
+
+def tm_loops_tdil(ctx, gauge, params, lt, spacing, phases=None, hpe=False, want_raw=False, check=True):
+    """Time-diluted loops: one source per phase p (timeslices t = p mod spacing)
+    of each noise vector, summed per noise vector, TSM over noise vectors.
+    dict(est_std, var_re_std, var_im_std, and with hpe est_hpe, var_re_hpe,
+    var_im_hpe (90, lt), NaN where not covered; optional raw_std_hp, raw_std_lp
+    (, raw_hpe_hp, raw_hpe_lp) per noise vector; stats, status)."""
+    ph = None if phases is None else np.ascontiguousarray(np.asarray(phases, dtype=np.int32))
+    extra = (int(spacing), None if ph is None else ph.ctypes.data, 0 if ph is None else int(ph.size), int(bool(hpe)))
+    names = ("std", "hpe") if hpe else ("std",)
+    return _loops2("tm_loops_tdil", names, ctx, gauge, params, lt, want_raw, check, extra)
 
 
 def tm_project_loops(raw: np.ndarray) -> np.ndarray:

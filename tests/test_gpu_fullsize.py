@@ -142,3 +142,22 @@ def test_fullsize_loops_hpe(oracle, big):
     for j in (0, 11):
         assert GU.relerr(r64["raw_hpe_lp"][j], ref["raw"]["lp_hpe"][j]) < 1e-10, j
         assert GU.relerr(r16["raw_hpe_lp"][j], ref["raw"]["lp_hpe"][j]) < 5e-3, j
+
+
+def test_fullsize_loops_tdil_one_timeslice(oracle, big):
+    """Full time dilution at one insertion timeslice (t = 8 of 64, one solve
+    per noise vector) at 32^3x64, FP16 LP in a batch of 12 with five
+    iterations: sampled noise vectors against the oracle; only t = 8 is
+    covered for the local loops."""
+    from paper_1401_6749_amd import tm
+
+    U, g = big
+    ctx = GU.context()
+    ref = oracle.loops_tdil(DIMS, -1, U, KAPPA, A, 105, 0, 12, 64, phases=[8], lp_fixed_iters=5,
+                            source_ids=[0, 11], return_raw=True)
+    P16 = tm.tsm_params(KAPPA, A, 105, 0, 12, lp=tm.solver_params("lp", fixed_iters=5, half="f16"), batch=12)
+    r = tm.tm_loops_tdil(ctx, g, P16, DIMS[3], 64, phases=[8], want_raw=True)
+    for j in (0, 11):
+        assert GU.relerr(r["raw_std_lp"][j][0], ref["raw"]["lp_std"][j][0]) < 5e-3, j
+    est = r["est_std"]
+    assert np.isfinite(est[:16, 8]).all() and np.isnan(est[:16, 7]).all() and np.isnan(est[:16, 9]).all()

@@ -401,3 +401,140 @@ def test_loops_hpe_rejects_small_extents():
     P = tm.tsm_params(0.12, 0.02, 1, 0, 2, lp=tm.solver_params("f64", tol=1e-2), batch=2)
     r = tm.tm_loops_hpe(ctx, g, P, dims[3], check=False)
     assert r["status"] == tm.TM_ERR_ARG
+
+
+def _same_nan(a, b):
+    return np.array_equal(np.isnan(a), np.isnan(b))
+
+
+def test_loops_tdil_f64_parity(oracle):
+    """Time dilution (Sec. 2.3) with the expansion on the FP64 path, full
+    dilution restricted to the phases {2, 3, 4}: per-noise-vector spin
+    matrices (summed over phases), the covered estimates of both estimators
+    and the NaN pattern of the uncovered ones match the oracle (1e-10)."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 4, 4, 8)
+    U = inputs.gauge_field(dims, seed=3)
+    g = GU.load(dims, U)
+    kappa, a = 0.12, 0.02
+    n_hp, n_lp = 2, 3
+    P = tm.tsm_params(kappa, a, 203, n_hp, n_lp, hp=tm.solver_params("f64", tol=1e-10),
+                      lp=tm.solver_params("f64", tol=1e-2), batch=5)
+    r = tm.tm_loops_tdil(ctx, g, P, dims[3], 8, phases=[2, 3, 4], hpe=True, want_raw=True)
+    ref = oracle.loops_tdil(dims, -1, U, kappa, a, 203, n_hp, n_lp, 8, phases=[2, 3, 4], hpe=True, hp_tol=1e-10,
+                            lp_tol=1e-2, return_raw=True)
+    for f in ("std", "hpe"):
+        for j in range(n_hp):
+            assert GU.relerr(r[f"raw_{f}_hp"][j], ref["raw"]["hp_" + f][j]) < 1e-10, (f, j)
+        for j in range(n_hp + n_lp):
+            assert GU.relerr(r[f"raw_{f}_lp"][j], ref["raw"]["lp_" + f][j]) < 1e-10, (f, j)
+        est, want = r["est_" + f], ref["est_" + f]
+        assert _same_nan(est, want) and _same_nan(r["var_re_" + f], ref["var_re_" + f]), f
+        ok = np.isfinite(want)
+        assert GU.relerr(est[ok], want[ok]) < 1e-10, f
+    assert np.isfinite(r["est_std"][:16, 3]).all() and np.isnan(r["est_std"][:16, 5]).all()
+    assert r["stats"]["hp_solves"] == 3 * n_hp and r["stats"]["lp_solves"] == 3 * (n_hp + n_lp)
+
+
+def test_loops_tdil_coherent_lp_matched_iterations(oracle):
+    """Coherent sources (spacing 4 on T = 16: four timeslices per source, all
+    four phases) on the FP16 LP path with five iterations per solve, against
+    the oracle's FP64 solves; batch 1 and batch 12 give equal bits."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (8, 8, 8, 16)
+    U = inputs.gauge_field(dims, seed=12)
+    g = GU.load(dims, U)
+    kappa, a = 0.1636, 0.0033
+    ref = oracle.loops_tdil(dims, -1, U, kappa, a, 8, 0, 6, 4, lp_fixed_iters=5, source_ids=[0, 5],
+                            return_raw=True)
+    out = []
+    for batch in (12, 1):
+        P = tm.tsm_params(kappa, a, 8, 0, 6, lp=tm.solver_params("lp", fixed_iters=5, half="f16"), batch=batch)
+        out.append(tm.tm_loops_tdil(ctx, g, P, dims[3], 4, want_raw=True))
+    for j in (0, 5):
+        assert GU.relerr(out[0]["raw_std_lp"][j], ref["raw"]["lp_std"][j]) < 5e-3, j
+    assert np.array_equal(out[0]["raw_std_lp"], out[1]["raw_std_lp"])
+    assert np.isfinite(out[0]["est_std"]).all()
+
+
+def test_loops_tdil_spacing_one_equals_undiluted():
+    """spacing 1: every source covers all timeslices, so the loops are
+    tm_loops_tsm's, bit for bit."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 4, 4, 8)
+    g = GU.load(dims, inputs.gauge_field(dims, seed=4))
+    P = tm.tsm_params(0.12, 0.02, 9, 2, 6, hp=tm.solver_params("mixed", tol=1e-10),
+                      lp=tm.solver_params("lp", tol=1e-2, half="f16"), batch=4)
+    r = tm.tm_loops_tdil(ctx, g, P, dims[3], 1)
+    ref = tm.tm_loops_tsm(ctx, g, P, dims[3])
+    assert np.array_equal(r["est_std"], ref["est"]) and np.array_equal(r["var_re_std"], ref["var_re"])
+
+
+def test_loops_tdil_rejects_bad_dilution():
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 4, 4, 8)
+    g = GU.load(dims, inputs.gauge_field(dims, seed=4))
+    P = tm.tsm_params(0.12, 0.02, 9, 0, 2, lp=tm.solver_params("f64", tol=1e-2), batch=2)
+    for spacing, phases in ((3, None), (0, None), (4, [1, 1]), (4, [4]), (16, None)):
+        r = tm.tm_loops_tdil(ctx, g, P, dims[3], spacing, phases=phases, check=False)
+        assert r["status"] == tm.TM_ERR_ARG, (spacing, phases)
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_half_store_flushes_subnormal_sites(prec):
+    """Half storage keeps a per-site FP32 scale; a site whose largest
+    component is below the smallest normal FP32 number is stored as zero
+    (its reciprocal would overflow), a site just above it keeps its values,
+    and every stored value is finite."""
+    torch = GU.torch_mod()
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 4, 4, 8)
+    V = int(np.prod(dims))
+    g = GU.load(dims, inputs.gauge_field(dims, seed=1))
+    psi = inputs.random_spinor(dims, 3)
+    psi[5] *= 3e-39 / np.abs(psi[5]).max()  # site maximum below the FP32 normal range
+    psi[6] *= 5e-38 / np.abs(psi[6]).max()  # normal, close to the bound
+    psi[7] = 0.0
+    fb = tm.tm_field_bytes(g, prec, True)
+    f = torch.zeros(fb, dtype=torch.uint8, device="cuda")
+    tm.tm_field_import(ctx, g, prec, 1, GU.to_dev(psi[None]), f)
+    canon = torch.zeros(1, V, 4, 3, 2, dtype=torch.float64, device="cuda")
+    tm.tm_field_export(ctx, g, prec, 1, f, canon)
+    torch.cuda.synchronize()
+    out = GU.from_dev(canon).reshape(V, 4, 3)
+    assert np.isfinite(out).all()
+    assert not out[5].any() and not out[7].any()
+    tol = 1e-3 if prec == "f16" else 8e-3
+    assert GU.relerr(out[6], psi[6]) < tol
+    assert GU.relerr(np.delete(out, [5, 6, 7], 0), np.delete(psi, [5, 6, 7], 0)) < tol
+
+
+def test_loops_tdil_lp_long_tail(oracle):
+    """A one-timeslice source on a long lattice with twelve FP16 LP iterations:
+    the half-precision fields grow tails of rounding residues ahead of the
+    exact support that fall below the FP32 normal range; the solve stays
+    finite and matches the oracle's FP64 solve with the same iterations."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (8, 8, 8, 48)
+    U = inputs.gauge_field(dims, seed=14)
+    g = GU.load(dims, U)
+    kappa, a = 0.1636, 0.0033
+    ref = oracle.loops_tdil(dims, -1, U, kappa, a, 9, 0, 2, 48, phases=[8], lp_fixed_iters=12, return_raw=True)
+    for half in ("f16", "bf16"):
+        P = tm.tsm_params(kappa, a, 9, 0, 2, lp=tm.solver_params("lp", fixed_iters=12, half=half), batch=2)
+        r = tm.tm_loops_tdil(ctx, g, P, dims[3], 48, phases=[8], want_raw=True)
+        for j in range(2):
+            assert np.isfinite(r["raw_std_lp"][j]).all()
+            assert GU.relerr(r["raw_std_lp"][j][0], ref["raw"]["lp_std"][j][0]) < (5e-3 if half == "f16" else 3e-2)
