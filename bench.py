@@ -313,9 +313,7 @@ def tsm_scan(tm, np, ctx, g, W):
     P = tm.tsm_params(W["kappa"], W["a"], seed, n_hp, n_lp, hp=hp, lp=tm.solver_params("lp", tol=1e-2, half=W["half"]),
                       batch=W["batch"])
     r = tm.tm_loops_tsm(ctx, g, P, lt, want_raw=True)
-    raw = r["raw"][..., 0] + 1j * r["raw"][..., 1]
-    ops = tm.tm_project_loops(raw)
-    hp_ops, lp_ops = ops[:n_hp], ops[n_hp:]
+    hp_ops, lp_ops = tm.tm_project_loops(r["raw_hp"]), tm.tm_project_loops(r["raw_lp"])
     d3 = 16 + 4 * 3 + 2  # i psibar gamma_3 D_3 psi: insertion gamma_3 (index 3), direction z
     rows = []
     for n in (30, 60, 120, 240, 480):
