@@ -491,7 +491,7 @@ static void job_from(Job &j, const tm_solver_params &p, double kappa, double a)
     j.tol = p.tol;
     j.max_iter = p.max_iter;
     j.fixed = p.fixed_iters;
-    j.delta = p.delta > 0 ? p.delta : 0.1;
+    j.delta = p.delta > 0 ? p.delta : 0.01;
 }
 
 extern "C" int tm_cg_solve(tm_context *ctx, const tm_gauge *G, double kappa, double a, const tm_solver_params *params,
@@ -840,12 +840,22 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         return TM_OK;
     };
     if (n_hp > 0) rc = add(kind_of(P->hp), P->hp, qh);
-    if (!rc) rc = add(kind_of(P->lp), P->lp, ql);
+    // LP sources split over lp_batches batches on their own streams, so one
+    // batch's host turnaround (harvest, refill) overlaps another's kernels
+    static const int lp_batches = std::max(1, std::min(4, [] {
+        const char *e = getenv("TM_LP_BATCHES");
+        return e ? atoi(e) : 1;
+    }()));
+    const int nlb = std::max(1, std::min<int>(lp_batches, (int)(ql.size() + batch - 1) / batch));
+    for (int k = 0; k < nlb && !rc; k++) {
+        std::vector<Job *> part(ql.begin() + ql.size() * k / nlb, ql.begin() + ql.size() * (k + 1) / nlb);
+        rc = add(kind_of(P->lp), P->lp, part);
+    }
     if (!rc) rc = run_jobs(bs, qs);
     double hp_end = 0, lp_end = 0;
     for (Batch *B : bs) {
         if (B == bs.front() && n_hp > 0) hp_end = B->t_last;
-        else lp_end = B->t_last;
+        else lp_end = std::max(lp_end, B->t_last);
         batch_destroy(B);
     }
     hipStream_t s = streams.empty() ? nullptr : streams.back();

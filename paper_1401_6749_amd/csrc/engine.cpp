@@ -370,7 +370,7 @@ static void fill_noise_run(Batch *b, int s0, int n, Job *const *jobs, int pp)
         P.a[i] = j->a;
         P.tol2[i] = j->fixed > 0 ? 0.0 : j->tol * j->tol;
         P.max_iter[i] = j->fixed > 0 ? j->fixed : j->max_iter;
-        const double delta = j->delta > 0 ? j->delta : 0.1;
+        const double delta = j->delta > 0 ? j->delta : 0.01;
         P.delta2[i] = delta * delta;
     }
     launch_z4_codes(g, Z, n, b->codes + (size_t)s0 * 2 * g.vh, s);
@@ -429,7 +429,7 @@ int batch_fill(Batch *b, int slot, Job *j)
     const bool mixed = b->kind == K_MIXED;
     const double tol2 = j->fixed > 0 ? 0.0 : j->tol * j->tol;
     const int maxit = j->fixed > 0 ? j->fixed : j->max_iter;
-    const double delta = j->delta > 0 ? j->delta : 0.1;
+    const double delta = j->delta > 0 ? j->delta : 0.01;
     double *part = b->partial + (size_t)slot * b->nblk;
     load_eta(b, slot, j);
     char *Ee = b->FA, *Eo = b->FA + b->h64;

@@ -709,14 +709,25 @@ struct WalkPos {
     int yy, zz;  // the thread's row and plane within the chunk
 };
 
+// Halo prefetch of the half-precision walk (bit 0: z halo, bit 1: y halo):
+// a thread on the chunk's edge loads its neighbour outside the chunk for the
+// next timeslice at the end of a step, when the block owning that
+// neighbour has just fetched it (its own next timeslice), instead of one
+// step later, when the L2 has usually dropped the line.
+#ifndef TM_WALK_HALO_PF
+#define TM_WALK_HALO_PF 0
+#endif
+
 // t neighbours: this thread's own site in timeslices t+-1, both in the
 // other LDS buffer (t-1 until the backward neighbour is done, t+1 after).
-template <int SP, int MU, bool FWD, bool DAG>
+// y/z neighbours outside the chunk come from the prefetched halo (hy, hz)
+// when there is one, else from global memory.
+template <int SP, int MU, bool FWD, bool DAG, class RawT>
 __device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, const Site &s, const WalkBuf<SP> &W,
-                                         const WalkPos &w, cpx<typename Real<SP>::T> acc[12])
+                                         const WalkPos &w, cpx<typename Real<SP>::T> acc[12], const RawT &hy,
+                                         const RawT &hz, int pf)
 {
     using T = typename Real<SP>::T;
-    using RawT = typename RawSel<SP, T>::type;
     const int n = nbr<MU, FWD ? 1 : -1>(A.g, s);
     if constexpr (MU == 3) {
         RawT raw;
@@ -737,6 +748,8 @@ __device__ __forceinline__ void walk_dir(const DslashArgs &A, const HopRes &R, c
             d = l + (q - (MU == 1 ? w.yy : w.zz)) * (MU == 1 ? A.g.lxh : A.g.lxh * A.wcy);
         }
         if (in) W.get(w.buf, d, raw);
+        else if (MU == 1 && (pf & 2)) raw = hy;
+        else if (MU == 2 && (pf & 1)) raw = hz;
         else raw.load(R.in, 0, A.g.vh, n);
         hop_compute<T, SP, MU, FWD, DAG, RawT>(A, R.gauge, s, n, raw, acc);
     }
@@ -791,10 +804,28 @@ __global__ __launch_bounds__(walk_max<SP>(), (walk_waves<SP, EPI>())) void k_dsl
     R.gauge = mkrsrc(A.gauge, A.gauge_span);
     R.in = mkrsrc(A.in + (size_t)slot * A.in_slot, A.in_span);
     R.lane = 0;
+    // halo prefetch roles: the one y (z) neighbour of this thread outside the
+    // chunk, if the chunk is at least two rows (planes) deep and does not
+    // span the dimension; pf bit set only for threads that have one
+    constexpr int PF = (SP == P16 || SP == PBF) ? TM_WALK_HALO_PF : 0;
+    int ydir = 0, zdir = 0, pf = 0;
+    if constexpr ((PF & 2) != 0)
+        if (A.wcy >= 2 && A.wcy < g.L[1]) ydir = yy == 0 ? -1 : (yy == A.wcy - 1 ? 1 : 0);
+    if constexpr ((PF & 1) != 0)
+        if (A.wcz >= 2 && A.wcz < g.L[2]) zdir = zz == 0 ? -1 : (zz == A.wcz - 1 ? 1 : 0);
+    pf = (ydir ? 2 : 0) | (zdir ? 1 : 0);
+    RawT hy{}, hz{};
+    // halo sites of timeslice t (same o) into hy / hz
+    auto halo_load = [&](int t) {
+        const Site s1 = site_of(g, t * g.st + o, A.out_par);
+        if (ydir) hy.load(R.in, 0, vh, ydir > 0 ? nbr<1, 1>(g, s1) : nbr<1, -1>(g, s1));
+        if (zdir) hz.load(R.in, 0, vh, zdir > 0 ? nbr<2, 1>(g, s1) : nbr<2, -1>(g, s1));
+    };
     {
         RawT r0, r1;
         r0.load(R.in, 0, vh, ((t0 + lt - 1) % lt) * g.st + o);
         r1.load(R.in, 0, vh, t0 * g.st + o);
+        if constexpr (PF != 0) halo_load(t0);
         W.put(1, threadIdx.x, r0);
         W.put(0, threadIdx.x, r1);
     }
@@ -813,20 +844,23 @@ __global__ __launch_bounds__(walk_max<SP>(), (walk_waves<SP, EPI>())) void k_dsl
         // t-1, which then takes timeslice t+1 (the forward t neighbour now and
         // the next step's spatial neighbours), so nxt is not held in registers
         // through the other seven neighbours.
-        walk_dir<SP, 3, false, DAG>(A, R, s, W, w, acc);
+        walk_dir<SP, 3, false, DAG>(A, R, s, W, w, acc, hy, hz, pf);
         W.put(w.buf ^ 1, threadIdx.x, nxt);
 #pragma unroll 1
         for (int d = 0; d < 7; d++) {
             switch (__builtin_amdgcn_readfirstlane(d)) {
-            case 0: walk_dir<SP, 0, true, DAG>(A, R, s, W, w, acc); break;
-            case 1: walk_dir<SP, 0, false, DAG>(A, R, s, W, w, acc); break;
-            case 2: walk_dir<SP, 1, true, DAG>(A, R, s, W, w, acc); break;
-            case 3: walk_dir<SP, 1, false, DAG>(A, R, s, W, w, acc); break;
-            case 4: walk_dir<SP, 2, true, DAG>(A, R, s, W, w, acc); break;
-            case 5: walk_dir<SP, 2, false, DAG>(A, R, s, W, w, acc); break;
-            default: walk_dir<SP, 3, true, DAG>(A, R, s, W, w, acc); break;
+            case 0: walk_dir<SP, 0, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+            case 1: walk_dir<SP, 0, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+            case 2: walk_dir<SP, 1, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+            case 3: walk_dir<SP, 1, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+            case 4: walk_dir<SP, 2, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+            case 5: walk_dir<SP, 2, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+            default: walk_dir<SP, 3, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
             }
         }
+        // next timeslice's halo, while its owners are reading it
+        if constexpr (PF != 0)
+            if (k + 1 < tw) halo_load(t + 1);
         const double part = epilogue<SP, EPI, IN2, 0, NT>(A, slot, cb, acc, kappa, a, alpha);
         if constexpr (EPI != EPI_PLAIN) {
             // one wave = one 64-site reduction tile

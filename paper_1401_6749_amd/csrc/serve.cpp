@@ -196,7 +196,7 @@ static int admit(tm_server *S, Request *R)
         j.tol = sp.tol;
         j.max_iter = sp.max_iter;
         j.fixed = sp.fixed_iters;
-        j.delta = sp.delta > 0 ? sp.delta : 0.1;
+        j.delta = sp.delta > 0 ? sp.delta : 0.01;
         j.raw_out = raw;
         j.want_true = R->P.want_true_resid;
         j.owner = R;
