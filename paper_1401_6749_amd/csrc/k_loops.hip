@@ -230,23 +230,25 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
 }
 
 // partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
-// blockIdx.y = source; the left vector is the source's codes (FIELD false) or
-// the field pair (l_even, l_odd) + i * l_stride; NK = 9 (all kinds) or 1 (local only)
+// block b handles source i = b mod n of site chunk b / n: the n sources of a
+// chunk run back to back and share its links in L2.  The left vector is the
+// source's codes (FIELD false) or the field pair (l_even, l_odd) +
+// i * l_stride; NK = 9 (all kinds) or 1 (local only)
 template <int SPS, bool FIELD, int NK>
 __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd,
                                                  size_t s_stride, const char *l_even, const char *l_odd,
                                                  size_t l_stride, const uint32_t *codes, double *cpart, int nchunk,
-                                                 size_t part_stride)
+                                                 size_t part_stride, int n)
 {
     __shared__ double lds[(CT / 64) * 32];
-    const int t = blockIdx.x / nchunk, chunk = blockIdx.x - t * nchunk;
-    const int i = blockIdx.y;
+    const int i = blockIdx.x % n, tc = blockIdx.x / n;
+    const int t = tc / nchunk, chunk = tc - t * nchunk;
     const char *s_fld[2] = {s_even + (size_t)i * s_stride, s_odd + (size_t)i * s_stride};
     LeftVec<SPS, FIELD> left;
     left.codes = FIELD ? nullptr : codes + (size_t)i * 2 * g.vh;
     left.fld[0] = FIELD ? l_even + (size_t)i * l_stride : nullptr;
     left.fld[1] = FIELD ? l_odd + (size_t)i * l_stride : nullptr;
-    double *dst = cpart + (size_t)i * part_stride + (size_t)blockIdx.x * 288;
+    double *dst = cpart + (size_t)i * part_stride + (size_t)tc * 288;
     double acc[32];
 #define TMK_KIND(K)                                                     \
     contract_kind<K, SPS, FIELD>(g, G, s_fld, left, t, chunk, acc);     \
@@ -297,12 +299,13 @@ static void contract_t(int sps, const Geom &g, const void *gauge, const char *s_
     const int nchunk = contract_nchunk(g);
     const int lt = g.L[3];
     const size_t ps = contract_part_doubles(g);
+    const unsigned nb = (unsigned)(lt * nchunk * n);
     if (sps == P32)
-        hipLaunchKernelGGL((k_contract<P32, FIELD, NK>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even,
-                           s_odd, s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps);
+        hipLaunchKernelGGL((k_contract<P32, FIELD, NK>), dim3(nb), dim3(CT), 0, s, g, gauge, s_even, s_odd, s_stride,
+                           l_even, l_odd, l_stride, codes, cpart, nchunk, ps, n);
     else
-        hipLaunchKernelGGL((k_contract<P64, FIELD, NK>), dim3(lt * nchunk, n), dim3(CT), 0, s, g, gauge, s_even,
-                           s_odd, s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps);
+        hipLaunchKernelGGL((k_contract<P64, FIELD, NK>), dim3(nb), dim3(CT), 0, s, g, gauge, s_even, s_odd, s_stride,
+                           l_even, l_odd, l_stride, codes, cpart, nchunk, ps, n);
     const int m = lt * NK * 16;
     hipLaunchKernelGGL(k_contract_final, dim3((m + 255) / 256, n), dim3(256), 0, s, cpart, nchunk, lt, raw, ps, sr,
                        si, NK);
