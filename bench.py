@@ -123,6 +123,30 @@ def measure_roofline(torch, tm, inputs, ctx, g, W, workload):
     }
 
 
+def kernel_rates(torch, tm, inputs, ctx, g, W):
+    """Hop launches in each storage precision (single RHS and 12 RHS at the
+    solver's slot pitch): microseconds per launch and algorithmic GB/s
+    (8 links + 2 spinors per output site and RHS, links once per launch)."""
+    dims = W["dims"]
+    vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    psi = tm.canonical_to_torch(inputs.random_spinor(dims, 2)[None])
+    out = []
+    for prec, nrhs in (("f64", 1), ("f32", 1), ("f16", 1), ("f64", 12), ("f32", 12), ("f16", 12), ("bf16", 12)):
+        fb = tm.tm_field_bytes(g, prec, True)
+        pitch = slot_pitch(fb)
+        fin = torch.zeros(nrhs * pitch, dtype=torch.uint8, device="cuda")
+        for r in range(nrhs):
+            tm.tm_field_import(ctx, g, prec, 1, psi, fin[r * pitch:r * pitch + fb])
+        fout = torch.zeros_like(fin)
+        t = event_time(torch, lambda: tm.tm_dslash_ex(ctx, g, "hop", W["kappa"], W["a"], prec, nrhs, fin, pitch,
+                                                       fout, pitch), 10) / 2
+        alg = vh * (8 * LINK_BYTES[prec] + nrhs * 2 * SPINOR_BYTES[prec])
+        out.append({"prec": prec, "nrhs": nrhs, "launch_us": round(t * 1e6, 1), "alg_GBs": round(alg / t / 1e9, 1),
+                    "frac_8TBs": round(alg / t / 1e9 / HBM_PEAK_GBS, 4)})
+        del fin, fout
+    return out
+
+
 def write_traffic(fetch_db: str, write_db: str, workload: str) -> None:
     """Per-launch HBM bytes of the roofline kernel from FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
@@ -365,20 +389,28 @@ def tsm_scan(tm, np, ctx, g, W):
 
 
 def r_hp_lp(tm, ctx, g, W, n=12):
-    """R_HP/LP: GPU time of n HP sources (solve + contraction) over that of n LP
-    sources, from one run with n LP-only sources and one with n HP sources (each
-    with its LP partner, as the method requires)."""
+    """R_HP/LP (the paper's Table 2 analogue): GPU time of n HP sources (solve
+    + contraction) over that of n LP sources, from one run with n LP-only
+    sources and one with n HP sources (each with its LP partner, as the method
+    requires); with the one-derivative contractions (value) and with the 16
+    local loops only (local)."""
     lt = W["dims"][3]
     hp = tm.solver_params("mixed", tol=1e-10)
     lp = tm.solver_params("lp", tol=1e-2, half=W["half"])
-    t = []
-    for nh, nl in ((0, n), (n, 0)):
-        P = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"] + 7, nh, nl, hp=hp, lp=lp, batch=W["batch"])
-        t0 = time.perf_counter()
-        tm.tm_loops_tsm(ctx, g, P, lt)
-        t.append(time.perf_counter() - t0)
-    return {"value": round((t[1] - t[0]) / t[0], 2), "t_lp_s": round(t[0], 3), "t_hp_plus_lp_s": round(t[1], 3),
-            "sources": n}
+    out = {}
+    for key, local in (("value", False), ("local", True)):
+        t = []
+        for nh, nl in ((0, n), (n, 0)):
+            P = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"] + 7, nh, nl, hp=hp, lp=lp, batch=W["batch"],
+                              local_only=local)
+            t0 = time.perf_counter()
+            tm.tm_loops_tsm(ctx, g, P, lt)
+            t.append(time.perf_counter() - t0)
+        out[key] = round((t[1] - t[0]) / t[0], 2)
+        out["t_lp_s" if not local else "t_lp_local_s"] = round(t[0], 3)
+        out["t_hp_plus_lp_s" if not local else "t_hp_plus_lp_local_s"] = round(t[1], 3)
+    out["sources"] = n
+    return out
 
 
 def serving_segment(tm, np, inputs, ctx, g_big, W, rate_big, n_req, budget_gb=32, load=0.8, seed=5):
@@ -411,33 +443,54 @@ def serving_segment(tm, np, inputs, ctx, g_big, W, rate_big, n_req, budget_gb=32
     arrivals = np.cumsum(rng.exponential(1.0 / lam, n_req))
     srv = tm.tm_serve_create(ctx, slots=W["batch"], workspace_budget=int(budget_gb) << 30)
     res = {}
+    stalled = False
+    # a request still missing this long after the last arrival is reported, not waited for
+    deadline = float(arrivals[-1]) + 20.0 * sum(r[4] for r in reqs) + 60.0
     try:
         t0 = time.perf_counter()
         k = 0
+        next_log = 10.0
         while len(res) < n_req:
             now = time.perf_counter() - t0
             while k < n_req and arrivals[k] <= now:
                 rc = tm.tm_serve_submit(srv, reqs[k][1], reqs[k][2], k)
                 if rc != 0:
-                    raise RuntimeError(f"serving request {k} rejected ({rc})")
+                    raise RuntimeError(f"serving request {k} rejected ({rc}): {tm.tm_last_error(ctx)}")
                 k += 1
             for r in tm.tm_serve_poll(srv):
                 res[r["tag"]] = r
+            if now > next_log:
+                st = tm.tm_serve_status_get(srv)
+                log(f"serving: {len(res)}/{n_req} done, {k} submitted at {now:.0f}s; queued {st['queued']}, "
+                    f"active {st['active']}, batches {st['batches']}, pending jobs {st['pending_jobs']}, "
+                    f"slots {st['running_slots']}, arena {st['arena_used'] >> 20}/{st['arena_size'] >> 20} MiB")
+                next_log += 10.0
+            if now > deadline:
+                stalled = True
+                missing = sorted(set(range(k)) - set(res))
+                raise RuntimeError(f"serving: requests {missing[:8]} (of {len(missing)}) not done after {now:.0f}s; "
+                                   f"server {tm.tm_serve_status_get(srv)}; last error: {tm.tm_last_error(ctx)}")
             time.sleep(0.0005)
         wall = time.perf_counter() - t0
         # one request again alone: its result must have the same bits
         probe = min(range(n_req), key=lambda i: reqs[i][4])
         tm.tm_serve_submit(srv, reqs[probe][1], reqs[probe][2], 10 ** 6)
         alone = None
+        t1 = time.perf_counter()
         while alone is None:
             for r in tm.tm_serve_poll(srv):
                 alone = r
+            if time.perf_counter() - t1 > 60.0:
+                stalled = True
+                raise RuntimeError(f"serving: the repeated request is not done after 60 s: {tm.tm_last_error(ctx)}")
             time.sleep(0.001)
     finally:
-        tm.tm_serve_destroy(srv)
-        for d in sizes[:3]:
-            for gp in pools[d]:
-                tm.tm_free_gauge(ctx, gp)
+        # a stalled server still owns its requests and their gauge fields: left to the process exit
+        if not stalled:
+            tm.tm_serve_destroy(srv)
+            for d in sizes[:3]:
+                for gp in pools[d]:
+                    tm.tm_free_gauge(ctx, gp)
     lat = np.array([res[i]["t_done"] - res[i]["t_submit"] for i in range(n_req)])
     wait = np.array([res[i]["t_admit"] - res[i]["t_submit"] for i in range(n_req)])
     n_src = sum(r[3] for r in reqs)
@@ -471,6 +524,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=40,
                     help="requests in the serving segment (0 skips it)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving segment (after one warm-up step)")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="serving arrival rate as a fraction of the volume-scaled capacity")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the precision, R_HP/LP and serving segments")
     ap.add_argument("--roofline-only", action="store_true",
@@ -530,8 +585,8 @@ def main():
         return
     if args.serving_only:
         rate = n_src / r["stats"]["seconds"]
-        print(json.dumps({"serving": serving_segment(tm, np, inputs, ctx, g, W, rate, args.serve_requests)}),
-              flush=True)
+        print(json.dumps({"serving": serving_segment(tm, np, inputs, ctx, g, W, rate, args.serve_requests,
+                                                     load=args.serve_load)}), flush=True)
         return
     torch.cuda.synchronize()
     ta = time.perf_counter()
@@ -576,6 +631,8 @@ def main():
             f"{plain['tsm_effective_speedup_local_median']:.1f}x deriv {plain['tsm_effective_speedup_deriv_median']:.1f}x")
 
     roofline = measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)
+    rates = kernel_rates(torch, tm, inputs, ctx, g, W)
+    log("hop rates: " + ", ".join(f"{r['prec']}x{r['nrhs']} {r['launch_us']}us {r['alg_GBs']}GB/s" for r in rates))
 
     precision = rhl = serving = oet = hpe = tdil = None
     if not args.no_extra:
@@ -591,11 +648,17 @@ def main():
         tdil = tdil_segment(tm, np, ctx, g, W)
         log(f"time dilution at t={tdil['t_ins']}: error ratio {tdil['error_ratio_tdil_local_median']:.2f}, "
             f"with HPE {tdil['error_ratio_tdil_hpe_local_median']:.2f} at equal solves")
-        log(f"precision and R_HP/LP segments in {time.perf_counter() - t0:.1f}s; R_HP/LP {rhl['value']}")
+        log(f"precision and R_HP/LP segments in {time.perf_counter() - t0:.1f}s; R_HP/LP {rhl['value']} "
+            f"(local only {rhl['local']})")
         if args.serve_requests > 0:
-            serving = serving_segment(tm, np, inputs, ctx, g, W, value, args.serve_requests)
-            log(f"serving: {serving['requests']} requests, p50 {serving['latency_p50_s']}s, "
-                f"p99 {serving['latency_p99_s']}s, {serving['sources_per_s']} sources/s")
+            try:
+                serving = serving_segment(tm, np, inputs, ctx, g, W, value, args.serve_requests, load=args.serve_load)
+            except RuntimeError as e:
+                serving = {"error": str(e)}
+                log(f"serving failed: {e}")
+            else:
+                log(f"serving: {serving['requests']} requests, p50 {serving['latency_p50_s']}s, "
+                    f"p99 {serving['latency_p99_s']}s, {serving['sources_per_s']} sources/s")
 
     # ---- CPU oracle on a bounded sample (one LP source at the same lattice) ----
     cpu = None
@@ -659,6 +722,7 @@ def main():
         "time_dilution": tdil,
         "serving": serving,
         "roofline": roofline,
+        "kernel_rates": rates,
         "cpu_baseline": cpu,
     }
     tm.tm_free_gauge(ctx, g)

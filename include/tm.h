@@ -235,6 +235,9 @@ typedef struct tm_tsm_params {
     tm_solver_params lp;       /* low-precision solver (usually LP truncated at 1e-2) */
     int batch;                 /* right-hand sides per multi-RHS launch (1..16, 0 -> 12) */
     int want_true_resid;       /* 1: compute |eta - M s|/|eta| for every solve */
+    int ops;                   /* 0: local and one-derivative loops; 1: the 16 local loops only
+                                  (ops 16..89 NaN, raw kinds 1..8 zero; one contraction pass).
+                                  Serving requests take 0 only. */
 } tm_tsm_params;
 
 typedef struct tm_tsm_stats {
@@ -383,6 +386,22 @@ int tm_serve_drain(tm_server *srv);
 void tm_result_free(tm_result *res);
 /* Seconds on the server clock (same clock as tm_result times). */
 double tm_serve_clock(tm_server *srv);
+
+/* Snapshot of the serving loop, published by the worker once per pass. */
+typedef struct tm_serve_status {
+    int queued;               /* submitted, not admitted */
+    int active;               /* admitted, not finished */
+    int finished;             /* finished, not yet polled */
+    int batches;              /* resident multi-RHS batches */
+    int in_flight;            /* batches with a chunk on the GPU */
+    int pending_jobs;         /* solves waiting for a slot */
+    int running_slots;        /* occupied slots over all batches */
+    int worker_error;         /* first error met by the worker (TM_OK if none) */
+    size_t arena_used, arena_size, arena_largest_free;
+    double t_snapshot;        /* server clock of the snapshot */
+} tm_serve_status;
+/* Copy the latest snapshot into *out.  Errors: TM_ERR_ARG. */
+int tm_serve_status_get(tm_server *srv, tm_serve_status *out);
 int tm_serve_destroy(tm_server *srv);
 
 /* ------------------------------------------------------------------ */

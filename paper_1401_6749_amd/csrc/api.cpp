@@ -714,6 +714,7 @@ int tsm_check(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P)
         return set_err(ctx, TM_ERR_ARG, "need n_hp >= 0, n_lp >= 0 and at least one source");
     if (P->n_hp + P->n_lp > (1 << 24)) return set_err(ctx, TM_ERR_ARG, "too many sources");
     if (P->batch < 0 || P->batch > MAX_SLOTS) return set_err(ctx, TM_ERR_ARG, "batch must be 0..%d", MAX_SLOTS);
+    if (P->ops != 0 && P->ops != 1) return set_err(ctx, TM_ERR_ARG, "ops must be 0 (all) or 1 (local only)");
     int rc = TM_OK;
     if (P->n_hp > 0 && (rc = check_solver(ctx, G, &P->hp))) return rc;
     if ((rc = check_solver(ctx, G, &P->lp))) return rc;
@@ -774,8 +775,8 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         nf * (src_raw + job_raw + src_ops + ops_per * 2) + (hpe ? raw_per + ops_per : 0) + mask_doubles;
     double *dbuf = (double *)dalloc(ctx, dev_doubles * sizeof(double));
     if (!dbuf) return set_err(ctx, TM_ERR_NOMEM, "tm_loops: no memory for per-source loops");
-    // the expansion's raw spin matrices carry the local kind only
-    if (hpe) {
+    // the expansion's (and a local-only run's) raw spin matrices carry the local kind only
+    if (hpe || P->ops == 1) {
         hipError_t e = hipMemsetAsync(dbuf, 0, dev_doubles * sizeof(double), nullptr);
         if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) {
@@ -811,6 +812,7 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         j.raw_out = job_out(0, is_hp, i, k);
         j.oet = oet;
         j.hpe = hpe;
+        j.local_only = P->ops == 1;
         j.raw_out2 = nf > 1 ? job_out(1, is_hp, i, k) : nullptr;
         j.want_true = P->want_true_resid;
         j.hp = is_hp;
@@ -873,7 +875,7 @@ int tsm_run(tm_context *ctx, const tm_gauge *G, const tm_tsm_params *P, double *
         bool masked[2] = {false, false};
         for (int f = 0; f < nf; f++) {
             unsigned char *m = mask.data() + (size_t)f * TM_N_OPS * lt;
-            valid_mask(lt, dil, hpe && f == 1, m);
+            valid_mask(lt, dil, (hpe && f == 1) || P->ops == 1, m);
             for (size_t q = 0; q < (size_t)TM_N_OPS * lt; q++) masked[f] |= m[q] == 0;
         }
         hipError_t e = hipMemcpyAsync(d_mask, mask.data(), mask.size(), hipMemcpyHostToDevice, s);

@@ -596,12 +596,14 @@ static void harvest_lp_run(Batch *b, int s0, int n)
         dsl_run(b, P32, false, EPI_PLAIN, CM_M, 0, so32, w, se32, w, re, w, j->kappa, 0.0, n);
         dsl_run(b, P32, false, EPI_PLAIN, CM_M, 1, se32, w, so32, w, ro, w, j->kappa, 0.0, n);
         launch_contract_lr(P32, g, b->G->links[P32], se32, so32, w, se32, so32, w, b->cpart, R, n, 0.0, -2.0 * j->a,
-                           s);
-        launch_contract_lr(P32, g, b->G->links[P32], re, ro, w, se32, so32, w, b->cpart, R2, n, 2.0, 0.0, s);
+                           s, j->local_only);
+        launch_contract_lr(P32, g, b->G->links[P32], re, ro, w, se32, so32, w, b->cpart, R2, n, 2.0, 0.0, s,
+                           j->local_only);
         return;
     }
     const uint32_t *codes = b->codes + (size_t)s0 * 2 * g.vh;
-    launch_contract(P32, g, b->G->links[P32], se32, so32, w, codes, b->cpart, R, n, s);
+    if (j->local_only) launch_contract_local(P32, g, se32, so32, w, codes, b->cpart, R, n, s);
+    else launch_contract(P32, g, b->G->links[P32], se32, so32, w, codes, b->cpart, R, n, s);
     if (j->hpe) {
         // (BH)^4 s: even part ((BH)_eo (BH)_oe)^2 s_e via FA (odd) into FD,
         // odd part ((BH)_oe (BH)_eo)^2 s_o via FA (even) into FB
@@ -680,11 +682,19 @@ static void harvest64(Batch *b, int slot, const SlotState &S, Job *j)
             RawOuts R{}, R2{};
             R.p[0] = j->raw_out;
             R2.p[0] = j->raw_out2;
-            launch_contract_lr(P64, g, b->G->links[P64], se, so, 0, se, so, 0, b->cpart, R, 1, 0.0, -2.0 * j->a, s);
-            launch_contract_lr(P64, g, b->G->links[P64], re, ro, 0, se, so, 0, b->cpart, R2, 1, 2.0, 0.0, s);
+            launch_contract_lr(P64, g, b->G->links[P64], se, so, 0, se, so, 0, b->cpart, R, 1, 0.0, -2.0 * j->a, s,
+                               j->local_only);
+            launch_contract_lr(P64, g, b->G->links[P64], re, ro, 0, se, so, 0, b->cpart, R2, 1, 2.0, 0.0, s,
+                               j->local_only);
         } else if (j->raw_out) {
             const uint32_t *codes = b->codes + (size_t)slot * 2 * g.vh;
-            launch_contract(P64, g, b->G->links[P64], se, so, codes, b->cpart, j->raw_out, s);
+            if (j->local_only) {
+                RawOuts R{};
+                R.p[0] = j->raw_out;
+                launch_contract_local(P64, g, se, so, 0, codes, b->cpart, R, 1, s);
+            } else {
+                launch_contract(P64, g, b->G->links[P64], se, so, codes, b->cpart, j->raw_out, s);
+            }
             if (j->hpe) {
                 // (BH)^4 s into FB = [even | odd] through FA (see harvest_lp_run)
                 char *ae = b->FA, *ao = b->FA + b->h64, *we = b->FB, *wo = b->FB + b->h64;
@@ -772,7 +782,7 @@ int batch_process(Batch *b, std::vector<Job *> &finished)
             static const int cap = run_cap("TM_HARVEST_RUN");
             while (s + n < S && n < std::min(b->wslots, cap) && done(s + n) && lp_harvest(b, b->slot_job[s + n]) &&
                    same_params(b->slot_job[s + n], j) && b->slot_job[s + n]->oet == j->oet &&
-                   b->slot_job[s + n]->hpe == j->hpe)
+                   b->slot_job[s + n]->hpe == j->hpe && b->slot_job[s + n]->local_only == j->local_only)
                 n++;
             harvest_lp_run(b, s, n);
         } else if (prep_prec(b, j) != P32) {

@@ -328,10 +328,14 @@ void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_ev
 
 void launch_contract_lr(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
                         size_t s_stride, const char *l_even, const char *l_odd, size_t l_stride, double *cpart,
-                        const RawOuts &raw, int n, double sr, double si, hipStream_t s)
+                        const RawOuts &raw, int n, double sr, double si, hipStream_t s, bool local_only)
 {
-    contract_t<true>(sps, g, gauge, s_even, s_odd, s_stride, l_even, l_odd, l_stride, nullptr, cpart, raw, n, sr, si,
-                     s);
+    if (local_only)
+        contract_t<true, 1>(sps, g, gauge, s_even, s_odd, s_stride, l_even, l_odd, l_stride, nullptr, cpart, raw, n,
+                            sr, si, s);
+    else
+        contract_t<true>(sps, g, gauge, s_even, s_odd, s_stride, l_even, l_odd, l_stride, nullptr, cpart, raw, n, sr,
+                         si, s);
 }
 
 void launch_contract_local(int sps, const Geom &g, const char *s_even, const char *s_odd, size_t s_stride,

@@ -92,6 +92,7 @@ struct tm_server {
     double t0 = 0;
     Mem mem;
     int worker_error = TM_OK;
+    tm_serve_status snap{};  // guarded by mu
 };
 
 static double sclock(tm_server *s) { return now_s() - s->t0; }
@@ -345,6 +346,26 @@ static void worker_main(tm_server *S)
             }
             i++;
         }
+        {
+            // publish a snapshot for tm_serve_status_get
+            tm_serve_status st{};
+            st.active = (int)S->active.size();
+            st.batches = (int)S->batches.size();
+            for (auto &kv : S->batches) {
+                st.in_flight += kv.second->b->in_flight ? 1 : 0;
+                st.pending_jobs += (int)kv.second->pending.size();
+                st.running_slots += batch_active(kv.second->b);
+            }
+            st.worker_error = S->worker_error;
+            st.arena_used = S->arena.used;
+            st.arena_size = S->arena.size;
+            st.arena_largest_free = S->arena.largest_free();
+            st.t_snapshot = sclock(S);
+            std::lock_guard<std::mutex> lk(S->mu);
+            st.queued = (int)S->queue.size();
+            st.finished = (int)S->finished.size();
+            S->snap = st;
+        }
         if (!progressed) {
             bool finalizing = false;
             for (Request *R : S->active) finalizing |= R->state == RQ_FINALIZING;
@@ -406,6 +427,8 @@ extern "C" int tm_serve_submit(tm_server *S, const tm_request *req)
     if (!S || !req || !req->gauge) return TM_ERR_ARG;
     int rc = tsm_check(S->ctx, req->gauge, &req->params);
     if (rc) return rc;
+    if (req->params.ops != 0)
+        return set_err(S->ctx, TM_ERR_ARG, "tm_serve_submit: requests compute all operators (ops 0)");
     Request *R = new Request();
     R->tag = req->tag;
     R->G = req->gauge;
@@ -497,6 +520,14 @@ extern "C" void tm_result_free(tm_result *r)
 }
 
 extern "C" double tm_serve_clock(tm_server *S) { return S ? sclock(S) : 0.0; }
+
+extern "C" int tm_serve_status_get(tm_server *S, tm_serve_status *out)
+{
+    if (!S || !out) return TM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->snap;
+    return TM_OK;
+}
 
 extern "C" int tm_serve_destroy(tm_server *S)
 {

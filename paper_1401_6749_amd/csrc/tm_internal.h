@@ -82,6 +82,7 @@ struct Job {
     bool oet = false;           // one-end trick estimators instead of eta^dag G s
     double *raw_out2 = nullptr; // one-end trick: the isoscalar part; HPE: eta^dag G (BH)^4 s (kind 0) [9][T][16][2]
     bool hpe = false;           // also the stochastic term of the hopping parameter expansion
+    bool local_only = false;    // local spin matrices only (kind 0)
     int tmod = 0, tph = 0;      // time dilution: eta only on the timeslices t = tph mod tmod (tmod 0: all)
     int want_true = 0;
     // output

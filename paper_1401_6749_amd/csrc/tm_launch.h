@@ -86,7 +86,7 @@ void launch_contract(int sps, const Geom &g, const void *gauge, const char *s_ev
 // in precision sps; raw = (sr + i si) * the spin-matrix sums
 void launch_contract_lr(int sps, const Geom &g, const void *gauge, const char *s_even, const char *s_odd,
                         size_t s_stride, const char *l_even, const char *l_odd, size_t l_stride, double *cpart,
-                        const RawOuts &raw, int n, double sr, double si, hipStream_t s);
+                        const RawOuts &raw, int n, double sr, double si, hipStream_t s, bool local_only = false);
 // local spin matrices only (kind 0 of raw[i]; other kinds untouched) of n
 // sources with Z4-code left vectors, as launch_contract
 void launch_contract_local(int sps, const Geom &g, const char *s_even, const char *s_odd, size_t s_stride,

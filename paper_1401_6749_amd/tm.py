@@ -75,7 +75,13 @@ class tm_solve_stats(ctypes.Structure):
 class tm_tsm_params(ctypes.Structure):
     _fields_ = [("kappa", c_double), ("two_kappa_mu", c_double), ("noise_seed", c_uint64), ("n_hp", c_int),
                 ("n_lp", c_int), ("hp", tm_solver_params), ("lp", tm_solver_params), ("batch", c_int),
-                ("want_true_resid", c_int)]
+                ("want_true_resid", c_int), ("ops", c_int)]
+
+
+class tm_serve_status(ctypes.Structure):
+    _fields_ = [("queued", c_int), ("active", c_int), ("finished", c_int), ("batches", c_int), ("in_flight", c_int),
+                ("pending_jobs", c_int), ("running_slots", c_int), ("worker_error", c_int), ("arena_used", c_size_t),
+                ("arena_size", c_size_t), ("arena_largest_free", c_size_t), ("t_snapshot", c_double)]
 
 
 class tm_tsm_stats(ctypes.Structure):
@@ -123,6 +129,7 @@ _sig = {
     "tm_loops_tdil": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_int, c_void_p, c_int, c_int,
                               c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(tm_tsm_stats)]),
     "tm_project_loops": (c_int, [c_int, c_int, c_void_p, c_void_p]),
+    "tm_serve_status_get": (c_int, [c_void_p, ctypes.POINTER(tm_serve_status)]),
     "tm_serve_create": (c_int, [c_void_p, c_int, c_size_t, ctypes.POINTER(c_void_p)]),
     "tm_serve_submit": (c_int, [c_void_p, ctypes.POINTER(tm_request)]),
     "tm_serve_footprint": (c_int, [c_void_p, ctypes.POINTER(tm_request), ctypes.POINTER(ctypes.c_size_t)]),
@@ -294,11 +301,12 @@ def tm_z4_source(ctx, dims, seed, src, out, stream=None):
                                   _stream(stream)), "tm_z4_source")
 
 
-def tsm_params(kappa, two_kappa_mu, noise_seed, n_hp, n_lp, hp=None, lp=None, batch=12, want_true_resid=0):
+def tsm_params(kappa, two_kappa_mu, noise_seed, n_hp, n_lp, hp=None, lp=None, batch=12, want_true_resid=0,
+               local_only=False):
     hp = hp if hp is not None else solver_params("mixed", tol=1e-10)
     lp = lp if lp is not None else solver_params("lp", tol=1e-2, half="f16")
     return tm_tsm_params(float(kappa), float(two_kappa_mu), int(noise_seed), int(n_hp), int(n_lp), hp, lp,
-                         int(batch), int(want_true_resid))
+                         int(batch), int(want_true_resid), 1 if local_only else 0)
 
 
 def _stats_dict(st):
@@ -442,6 +450,15 @@ def tm_serve_drain(srv):
 
 def tm_serve_clock(srv):
     return float(_lib.tm_serve_clock(srv))
+
+
+def tm_serve_status_get(srv):
+    """Latest snapshot of the serving loop as a dict."""
+    st = tm_serve_status()
+    rc = _lib.tm_serve_status_get(srv, ctypes.byref(st))
+    if rc != TM_OK:
+        raise TMError(rc, "tm_serve_status_get")
+    return {k: getattr(st, k) for k, _ in tm_serve_status._fields_}
 
 
 def tm_serve_destroy(srv):

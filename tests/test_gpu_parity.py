@@ -538,3 +538,34 @@ def test_loops_tdil_lp_long_tail(oracle):
         for j in range(2):
             assert np.isfinite(r["raw_std_lp"][j]).all()
             assert GU.relerr(r["raw_std_lp"][j][0], ref["raw"]["lp_std"][j][0]) < (5e-3 if half == "f16" else 3e-2)
+
+
+def test_loops_local_only_matches_full_run():
+    """ops = 1 (local loops only): the 16 local estimates and variances are
+    bit-identical to those of the full run (same contraction pass), the
+    operators with a link are NaN and the raw derivative kinds zero, for the
+    standard estimator (mixed HP + FP16 LP) and the one-end trick; serving
+    requests reject it."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (4, 4, 4, 8)
+    g = GU.load(dims, inputs.gauge_field(dims, seed=6))
+    kw = dict(hp=tm.solver_params("mixed", tol=1e-10), lp=tm.solver_params("lp", tol=1e-2, half="f16"), batch=4)
+    full = tm.tm_loops_tsm(ctx, g, tm.tsm_params(0.12, 0.02, 33, 2, 6, **kw), dims[3], want_raw=True)
+    loc = tm.tm_loops_tsm(ctx, g, tm.tsm_params(0.12, 0.02, 33, 2, 6, local_only=True, **kw), dims[3], want_raw=True)
+    assert np.array_equal(loc["est"][:16], full["est"][:16])
+    assert np.array_equal(loc["var_re"][:16], full["var_re"][:16])
+    assert np.isnan(loc["est"][16:]).all() and np.isnan(loc["var_im"][16:]).all()
+    assert not loc["raw_lp"][:, 1:].any() and np.array_equal(loc["raw_lp"][:, 0], full["raw_lp"][:, 0])
+    ofull = tm.tm_loops_oet(ctx, g, tm.tsm_params(0.12, 0.02, 33, 2, 6, **kw), dims[3])
+    oloc = tm.tm_loops_oet(ctx, g, tm.tsm_params(0.12, 0.02, 33, 2, 6, local_only=True, **kw), dims[3])
+    for f in ("vv", "ws"):
+        assert np.array_equal(oloc["est_" + f][:16], ofull["est_" + f][:16])
+        assert np.isnan(oloc["est_" + f][16:]).all()
+    srv = tm.tm_serve_create(ctx, slots=4, workspace_budget=1 << 32)
+    try:
+        rc = tm.tm_serve_submit(srv, g, tm.tsm_params(0.12, 0.02, 33, 0, 2, local_only=True, **kw), 1)
+        assert rc == tm.TM_ERR_ARG
+    finally:
+        tm.tm_serve_destroy(srv)
