@@ -57,13 +57,14 @@ def _hop_12(g, prec, psis):
 
 
 def test_fullsize_hop_12rhs(oracle, big):
-    """FP64, FP32 and FP16 hop at 32^3x64, 12 RHS per launch: every RHS against
-    the oracle's FP64 hop of the same input (FP64 <= 1e-14; FP32 / FP16 within
-    their storage rounding, as on the small lattices)."""
+    """FP64, FP32, FP16 and BF16 hop at 32^3x64, 12 RHS per launch: RHS against
+    the oracle's FP64 hop of the same input (FP64 <= 1e-14; FP32 / FP16 / BF16
+    within their storage rounding, as on the small lattices)."""
     U, g = big
     psis = [inputs.random_spinor(DIMS, 21), inputs.random_spinor(DIMS, 22)]
     want = [oracle.dhop(DIMS, -1, U, p) for p in psis]
-    for prec, tol, rhs in (("f64", 1e-14, (0, 1, 11)), ("f32", 2e-6, (0, 11)), ("f16", 3e-3, range(12))):
+    for prec, tol, rhs in (("f64", 1e-14, (0, 1, 11)), ("f32", 2e-6, (0, 11)), ("f16", 3e-3, range(12)),
+                           ("bf16", 2e-2, (0, 5, 11))):
         export = _hop_12(g, prec, psis)
         first = {}
         for r in rhs:

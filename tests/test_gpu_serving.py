@@ -85,6 +85,15 @@ def test_serving_admission_under_small_budget():
     try:
         for k, g in enumerate(gs):
             assert tm.tm_serve_submit(srv, g, P, k) == 0
+        # the worker's snapshot: the arena within its budget (a finishing request may overlap the next)
+        import time as _time
+        for _ in range(20):
+            st = tm.tm_serve_status_get(srv)
+            if st["t_snapshot"] > 0:  # published by the worker
+                assert st["arena_size"] == need * 3 // 2
+            assert st["active"] <= 2 and st["arena_used"] <= st["arena_size"]
+            assert st["queued"] + st["active"] + st["finished"] <= 3 and st["worker_error"] == 0
+            _time.sleep(0.005)
         res = _wait_all(tm, srv, 3)
         assert all(r["status"] == 0 for r in res.values())
         ordered = sorted(res.values(), key=lambda r: r["t_admit"])
