@@ -527,7 +527,7 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="serving arrival rate as a fraction of the volume-scaled capacity")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the precision, R_HP/LP and serving segments")
+                    help="skip the hop-rate, precision, R_HP/LP, estimator-variant and serving segments")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the copy calibration and the roofline kernel (for counter runs)")
     ap.add_argument("--scan", metavar="OUT_JSON",
@@ -631,8 +631,10 @@ def main():
             f"{plain['tsm_effective_speedup_local_median']:.1f}x deriv {plain['tsm_effective_speedup_deriv_median']:.1f}x")
 
     roofline = measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)
-    rates = kernel_rates(torch, tm, inputs, ctx, g, W)
-    log("hop rates: " + ", ".join(f"{r['prec']}x{r['nrhs']} {r['launch_us']}us {r['alg_GBs']}GB/s" for r in rates))
+    rates = None
+    if not args.no_extra:
+        rates = kernel_rates(torch, tm, inputs, ctx, g, W)
+        log("hop rates: " + ", ".join(f"{r['prec']}x{r['nrhs']} {r['launch_us']}us {r['alg_GBs']}GB/s" for r in rates))
 
     precision = rhl = serving = oet = hpe = tdil = None
     if not args.no_extra:
