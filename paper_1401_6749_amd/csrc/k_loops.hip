@@ -88,9 +88,12 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 }
 
 // ---------------------------------------------------------------------------
-// Contractions.  A block owns a chunk of CPB sites of one timeslice (both
-// parities); each thread accumulates its sites, the block reduces in a fixed
-// order and writes one partial per (timeslice, chunk); a second kernel sums
+// Contractions.  A block owns a chunk of CPB sites of one timeslice (sites
+// of parity 0, then parity 1, each in cb order) for one source.  For FP32
+// solutions it has one wave per kind of spin matrix: the nine waves walk the
+// same sites at the same time, so the solution, the links and the codes of a
+// site come from HBM once and the other kinds hit the caches.  Each lane accumulates its sites, the wave reduces in a fixed order
+// and writes one partial per (timeslice, chunk, kind); a second kernel sums
 // the chunks of each timeslice in order and applies one complex factor.
 //   kind 0:      P_ab  = sum conj(l_a) . s_b
 //   kind 1+nu:   F_ab  = sum conj(l_a(x)) . [U_nu(x) s(x+nu)]_b
@@ -99,30 +102,37 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 // 2^-1/2), or, for the one-end trick, a field: the solution itself (factor
 // -2ia, isovector) with s the solution or D_W applied to it (factor 2).
 // ---------------------------------------------------------------------------
-constexpr int CT = 128;        // threads per contraction block
-constexpr int SPT = 8;         // sites per thread (amortises the block reductions)
-constexpr int CPB = CT * SPT;  // sites per block
+// waves per SIMD the register allocation must allow: a block of nine waves
+// needs three on one SIMD
+#ifndef TM_CONTRACT_WAVES
+#define TM_CONTRACT_WAVES 3
+#endif
+constexpr int SPT = 16;        // sites per lane (amortises the wave reductions)
+constexpr int CPB = 64 * SPT;  // sites per block
 
 int contract_nchunk(const Geom &g) { return (2 * g.v3h + CPB - 1) / CPB; }
 
-// reduce NV doubles across the block (fixed order) and write them to dst
-template <int NV>
-__device__ __forceinline__ void block_write(double (&acc)[NV], double *lds, double *dst)
+// Wave sums of a lane's 32 accumulators by recursive halving: in the
+// exchange over lane bit b (b = 5 down to 1) a lane keeps the half of its
+// values that bit selects and adds its partner's copy of that half; then
+// lanes 2i and 2i+1 hold the total of value i, and lane 2i writes it.  The
+// order is fixed, so every call gives the same bits.
+__device__ __forceinline__ void wave_write32(double (&v)[32], double *dst)
 {
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int l = (int)threadIdx.x & 63;
 #pragma unroll
-    for (int k = 0; k < NV; k++) {
-        const double v = wave_sum(acc[k]);
-        if (l == 0) lds[w * NV + k] = v;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < NV; k += CT) {
-        double s = 0.0;
+    for (int e = 4; e >= 0; e--) {
+        const int h = 1 << e;  // values kept
+        const bool up = (l & (2 * h)) != 0;
 #pragma unroll
-        for (int q = 0; q < CT / 64; q++) s += lds[q * NV + k];
-        dst[k] = s;
+        for (int j = 0; j < h; j++) {
+            const double send = up ? v[j] : v[j + h];
+            const double keep = up ? v[j + h] : v[j];
+            v[j] = keep + __shfl_xor(send, 2 * h, 64);
+        }
     }
-    __syncthreads();
+    const double tot = v[0] + __shfl_xor(v[0], 1, 64);
+    if ((l & 1) == 0) dst[l >> 1] = tot;
 }
 
 __device__ __forceinline__ bool contract_site(const Geom &g, int t, int q, int &par, int &cb)
@@ -162,10 +172,11 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
     using T = typename Real<SPS>::T;
 #pragma unroll
     for (int k = 0; k < 32; k++) acc[k] = 0.0;
+    const int lane = (int)threadIdx.x & 63;
 #pragma unroll 1
     for (int k = 0; k < SPT; k++) {
         int par, cb;
-        if (!contract_site(g, t, chunk * CPB + k * CT + threadIdx.x, par, cb)) continue;
+        if (!contract_site(g, t, chunk * CPB + k * 64 + lane, par, cb)) continue;
         if constexpr (KIND == 0) {
             cpx<T> lv[12], sv[12];
             left.get(g, par, cb, lv);
@@ -229,19 +240,31 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
     }
 }
 
-// partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
-// block b handles source i = b mod n of site chunk b / n: the n sources of a
-// chunk run back to back and share its links in L2.  The left vector is the
-// source's codes (FIELD false) or the field pair (l_even, l_odd) +
-// i * l_stride; NK = 9 (all kinds) or 1 (local only)
-template <int SPS, bool FIELD, int NK>
-__global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd,
-                                                 size_t s_stride, const char *l_even, const char *l_odd,
-                                                 size_t l_stride, const uint32_t *codes, double *cpart, int nchunk,
-                                                 size_t part_stride, int n)
+// Waves per contraction block: one per kind for FP32 solutions; FP64 ones
+// (registers for FP64 products) take one wave that computes the kinds in turn.
+template <int SPS, int NK>
+constexpr int contract_waves()
 {
-    __shared__ double lds[(CT / 64) * 32];
-    const int i = blockIdx.x % n, tc = blockIdx.x / n;
+    return SPS == P32 ? NK : 1;
+}
+
+// partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
+// Logical block l handles source i = l mod n of site chunk l / n: the n
+// sources of a chunk run back to back on one XCD (the hardware hands block b
+// to XCD b mod 8, so l = (b mod 8) * per + b / 8 gives each XCD a contiguous
+// range of logical blocks) and share the chunk's links in its L2.  The left
+// vector is the source's codes (FIELD false) or the field pair
+// (l_even, l_odd) + i * l_stride; NK = 9 (all kinds) or 1 (local only).
+template <int SPS, bool FIELD, int NK>
+__global__ __launch_bounds__((64 * contract_waves<SPS, NK>()), (contract_waves<SPS, NK>() > 1 ? TM_CONTRACT_WAVES : 1))
+void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd, size_t s_stride, const char *l_even,
+                const char *l_odd, size_t l_stride, const uint32_t *codes, double *cpart, int nchunk,
+                size_t part_stride, int n, int total)
+{
+    const int per = (total + 7) >> 3;
+    const int l = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+    if (l >= total) return;  // uniform over the block
+    const int i = l % n, tc = l / n;
     const int t = tc / nchunk, chunk = tc - t * nchunk;
     const char *s_fld[2] = {s_even + (size_t)i * s_stride, s_odd + (size_t)i * s_stride};
     LeftVec<SPS, FIELD> left;
@@ -252,9 +275,11 @@ __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const ch
     double acc[32];
 #define TMK_KIND(K)                                                     \
     contract_kind<K, SPS, FIELD>(g, G, s_fld, left, t, chunk, acc);     \
-    block_write<32>(acc, lds, dst + (K) * 32);
-    TMK_KIND(0)
-    if constexpr (NK == 9) {
+    wave_write32(acc, dst + (K) * 32);
+    if constexpr (NK == 1) {
+        TMK_KIND(0)
+    } else if constexpr (contract_waves<SPS, NK>() == 1) {
+        TMK_KIND(0)
         TMK_KIND(1)
         TMK_KIND(2)
         TMK_KIND(3)
@@ -263,6 +288,19 @@ __global__ __launch_bounds__(CT) void k_contract(Geom g, const void *G, const ch
         TMK_KIND(6)
         TMK_KIND(7)
         TMK_KIND(8)
+    } else {
+        // wave w computes kind w
+        switch (__builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6)) {
+        case 0: TMK_KIND(0) break;
+        case 1: TMK_KIND(1) break;
+        case 2: TMK_KIND(2) break;
+        case 3: TMK_KIND(3) break;
+        case 4: TMK_KIND(4) break;
+        case 5: TMK_KIND(5) break;
+        case 6: TMK_KIND(6) break;
+        case 7: TMK_KIND(7) break;
+        default: TMK_KIND(8) break;
+        }
     }
 #undef TMK_KIND
 }
@@ -299,13 +337,16 @@ static void contract_t(int sps, const Geom &g, const void *gauge, const char *s_
     const int nchunk = contract_nchunk(g);
     const int lt = g.L[3];
     const size_t ps = contract_part_doubles(g);
-    const unsigned nb = (unsigned)(lt * nchunk * n);
+    const int total = lt * nchunk * n;
+    const unsigned nb = (unsigned)(8 * ((total + 7) / 8));
     if (sps == P32)
-        hipLaunchKernelGGL((k_contract<P32, FIELD, NK>), dim3(nb), dim3(CT), 0, s, g, gauge, s_even, s_odd, s_stride,
-                           l_even, l_odd, l_stride, codes, cpart, nchunk, ps, n);
+        hipLaunchKernelGGL((k_contract<P32, FIELD, NK>), dim3(nb), dim3(64 * contract_waves<P32, NK>()), 0, s, g,
+                           gauge, s_even, s_odd, s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps, n,
+                           total);
     else
-        hipLaunchKernelGGL((k_contract<P64, FIELD, NK>), dim3(nb), dim3(CT), 0, s, g, gauge, s_even, s_odd, s_stride,
-                           l_even, l_odd, l_stride, codes, cpart, nchunk, ps, n);
+        hipLaunchKernelGGL((k_contract<P64, FIELD, NK>), dim3(nb), dim3(64 * contract_waves<P64, NK>()), 0, s, g,
+                           gauge, s_even, s_odd, s_stride, l_even, l_odd, l_stride, codes, cpart, nchunk, ps, n,
+                           total);
     const int m = lt * NK * 16;
     hipLaunchKernelGGL(k_contract_final, dim3((m + 255) / 256, n), dim3(256), 0, s, cpart, nchunk, lt, raw, ps, sr,
                        si, NK);
