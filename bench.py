@@ -565,7 +565,7 @@ def main():
         tm.tm_destroy(ctx)
         return
 
-    hp = tm.solver_params("mixed", tol=1e-10, delta=0.01)
+    hp = tm.solver_params("mixed", tol=1e-10, delta=1e-3)
     lp = tm.solver_params("lp", tol=1e-2, half=W["half"])
     P = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"], W["n_hp"], W["n_lp"], hp=hp, lp=lp, batch=W["batch"])
     n_src = W["n_hp"] + W["n_lp"]
@@ -705,7 +705,7 @@ def main():
             "two_kappa_mu": W["a"],
             "n_hp": W["n_hp"],
             "n_lp": W["n_lp"],
-            "hp": "mixed FP32 CG with FP64 reliable updates (delta 0.01), tol 1e-10",
+            "hp": "mixed FP32 CG with FP64 reliable updates (delta 0.001), tol 1e-10",
             "lp": (f"{W['half']} storage; Dslash: FP32 arithmetic ("
                    + ("FP32 FMAs with the f16 operands widened inside the instruction"
                       if W["half"] == "f16" else "bf16 widened to FP32")

@@ -181,7 +181,7 @@ typedef struct tm_solver_params {
     double tol;            /* stop at |r_k| <= tol*|r_0| on Mhat^dag Mhat x = Mhat^dag bhat */
     int max_iter;          /* iteration cap (TM_ERR_NOCONV when reached) */
     int fixed_iters;       /* > 0: run exactly this many iterations, ignore tol */
-    double delta;          /* MIXED: reliable update when |r| < delta*|r at last update| (0 -> 0.01); convergence is always confirmed on the FP64 true residual */
+    double delta;          /* MIXED: reliable update when |r| < delta*|r at last update| (0 -> 0.001); convergence is always confirmed on the FP64 true residual */
     int chunk;             /* iterations per device launch chunk between host checks (0 -> auto) */
 } tm_solver_params;
 

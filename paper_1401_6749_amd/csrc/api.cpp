@@ -491,7 +491,7 @@ static void job_from(Job &j, const tm_solver_params &p, double kappa, double a)
     j.tol = p.tol;
     j.max_iter = p.max_iter;
     j.fixed = p.fixed_iters;
-    j.delta = p.delta > 0 ? p.delta : 0.01;
+    j.delta = p.delta > 0 ? p.delta : TM_DEFAULT_DELTA;
 }
 
 extern "C" int tm_cg_solve(tm_context *ctx, const tm_gauge *G, double kappa, double a, const tm_solver_params *params,

@@ -370,7 +370,7 @@ static void fill_noise_run(Batch *b, int s0, int n, Job *const *jobs, int pp)
         P.a[i] = j->a;
         P.tol2[i] = j->fixed > 0 ? 0.0 : j->tol * j->tol;
         P.max_iter[i] = j->fixed > 0 ? j->fixed : j->max_iter;
-        const double delta = j->delta > 0 ? j->delta : 0.01;
+        const double delta = j->delta > 0 ? j->delta : TM_DEFAULT_DELTA;
         P.delta2[i] = delta * delta;
     }
     launch_z4_codes(g, Z, n, b->codes + (size_t)s0 * 2 * g.vh, s);
@@ -381,9 +381,13 @@ static void fill_noise_run(Batch *b, int s0, int n, Job *const *jobs, int pp)
     dsl_run(b, pp, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, w, nullptr, 0, To, w, kappa, a, n);
     dsl_run(b, pp, true, EPI_NORM, CM_MHAT_DAG, 0, To, w, Be, w, Ce, w, kappa, a, n, part);
     launch_slot_start(b->st + s0, part, b->nblk, P, n, s);
-    launch_convert(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->hxr, n, s);
-    launch_convert(pp, b->sp, g, Ce, w, b->p + s0 * b->hsp, b->hsp, n, s);
-    launch_zero(b->xr, g, b->x + s0 * b->hxr, b->hxr, n, s);
+    if (b->xr == b->sp && b->hxr == b->hsp) {
+        launch_cg_start(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->p + s0 * b->hsp, b->x + s0 * b->hxr, b->hxr, n, s);
+    } else {
+        launch_convert(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->hxr, n, s);
+        launch_convert(pp, b->sp, g, Ce, w, b->p + s0 * b->hsp, b->hsp, n, s);
+        launch_zero(b->xr, g, b->x + s0 * b->hxr, b->hxr, n, s);
+    }
     if (mixed) {
         launch_convert(P64, P64, g, Ce, w, b->b64 + s0 * b->h64, b->h64, n, s);
         launch_zero(P64, g, b->x64 + s0 * b->h64, b->h64, n, s);
@@ -429,7 +433,7 @@ int batch_fill(Batch *b, int slot, Job *j)
     const bool mixed = b->kind == K_MIXED;
     const double tol2 = j->fixed > 0 ? 0.0 : j->tol * j->tol;
     const int maxit = j->fixed > 0 ? j->fixed : j->max_iter;
-    const double delta = j->delta > 0 ? j->delta : 0.01;
+    const double delta = j->delta > 0 ? j->delta : TM_DEFAULT_DELTA;
     double *part = b->partial + (size_t)slot * b->nblk;
     load_eta(b, slot, j);
     char *Ee = b->FA, *Eo = b->FA + b->h64;

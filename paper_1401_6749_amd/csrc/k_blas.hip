@@ -268,6 +268,44 @@ void launch_zero(int p, const Geom &g, char *f, size_t slot, int nslot, hipStrea
     }
 }
 
+// Start of a CG solve: r = p = rhs (rounded to precision PO, as k_convert
+// rounds), x = 0 (as k_zero), reading rhs once.
+template <int PI, int PO>
+__global__ __launch_bounds__(BLOCK) void k_cg_start(Geom g, const char *in, size_t in_slot, char *r, char *p, char *x,
+                                                    size_t o_slot)
+{
+    const int cb = blockIdx.x * BLOCK + threadIdx.x;
+    if (cb >= g.vh) return;
+    const size_t so = (size_t)blockIdx.y * o_slot;
+    cpx<double> v[12];
+    SpinorIO<PI>::load(in + (size_t)blockIdx.y * in_slot, g.vh, cb, v);
+    SpinorIO<PO>::store(r + so, g.vh, cb, v);
+    SpinorIO<PO>::store(p + so, g.vh, cb, v);
+#pragma unroll
+    for (int k = 0; k < 12; k++) v[k] = cpx<double>{0.0, 0.0};
+    SpinorIO<PO>::store(x + so, g.vh, cb, v);
+}
+
+template <int PI>
+static void cg_start_from(int po, const Geom &g, const char *in, size_t is, char *r, char *p, char *x, size_t os,
+                          int nslot, hipStream_t s)
+{
+    dim3 grid(nblk_of(g), nslot);
+    switch (po) {
+    case P64: hipLaunchKernelGGL((k_cg_start<PI, P64>), grid, dim3(BLOCK), 0, s, g, in, is, r, p, x, os); break;
+    case P32: hipLaunchKernelGGL((k_cg_start<PI, P32>), grid, dim3(BLOCK), 0, s, g, in, is, r, p, x, os); break;
+    case P16: hipLaunchKernelGGL((k_cg_start<PI, P16>), grid, dim3(BLOCK), 0, s, g, in, is, r, p, x, os); break;
+    case PBF: hipLaunchKernelGGL((k_cg_start<PI, PBF>), grid, dim3(BLOCK), 0, s, g, in, is, r, p, x, os); break;
+    }
+}
+
+void launch_cg_start(int pin, int pout, const Geom &g, const char *in, size_t in_slot, char *r, char *p, char *x,
+                     size_t out_slot, int nslot, hipStream_t s)
+{
+    if (pin == P64) cg_start_from<P64>(pout, g, in, in_slot, r, p, x, out_slot, nslot, s);
+    else cg_start_from<P32>(pout, g, in, in_slot, r, p, x, out_slot, nslot, s);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_accum_x(Geom g, char *x64, const char *x32, char *x32z, size_t s64,
                                                    size_t s32)
 {

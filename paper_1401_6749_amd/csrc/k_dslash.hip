@@ -775,7 +775,9 @@ constexpr int walk_waves()
                        : EPI == EPI_CGUPD ? TM_WALK_WAVES_F16_CG : TM_WALK_WAVES_F16;
 }
 
-template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, bool NT>
+// SRC bit 1: the site-local input is eta decoded from Z4 codes (the
+// reconstruction of noise solves), as in k_dslash.
+template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, bool NT, int SRC = 0>
 __global__ __launch_bounds__(walk_max<SP>(), (walk_waves<SP, EPI>())) void k_dslash_walk(const DslashArgs A)
 {
     using T = typename Real<SP>::T;
@@ -861,7 +863,7 @@ __global__ __launch_bounds__(walk_max<SP>(), (walk_waves<SP, EPI>())) void k_dsl
         // next timeslice's halo, while its owners are reading it
         if constexpr (PF != 0)
             if (k + 1 < tw) halo_load(t + 1);
-        const double part = epilogue<SP, EPI, IN2, 0, NT>(A, slot, cb, acc, kappa, a, alpha);
+        const double part = epilogue<SP, EPI, IN2, SRC, NT>(A, slot, cb, acc, kappa, a, alpha);
         if constexpr (EPI != EPI_PLAIN) {
             // one wave = one 64-site reduction tile
             const double v = wave_sum(part);
@@ -944,7 +946,7 @@ inline int lds_twalk()
     return tw;
 }
 
-template <int SP, bool DAG, int EPI, bool IN2>
+template <int SP, bool DAG, int EPI, bool IN2, int SRC = 0>
 static bool launch_walk(DslashArgs A, hipStream_t s)
 {
     {
@@ -964,7 +966,9 @@ static bool launch_walk(DslashArgs A, hipStream_t s)
         const int total = A.nblk_site * A.nslot;
         const int grid = A.swz ? 8 * ((total + 7) / 8) : total;
         // outputs are streamed past L2 (non-temporal), keeping it for the halo lines
-        if (A.st)
+        if constexpr (SRC != 0)
+            hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, false, true, SRC>), dim3(grid), dim3(cs), 0, s, A);
+        else if (A.st)
             hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, true, true>), dim3(grid), dim3(cs), 0, s, A);
         else
             hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, false, true>), dim3(grid), dim3(cs), 0, s, A);
@@ -1017,9 +1021,15 @@ static void launch_sp(bool dag, int epi, bool in2, const DslashArgs &A, hipStrea
 }
 
 // Z4-code sources (prep and reconstruction of noise solves), FP32 and FP64.
+// The reconstruction (hop input a field, site-local input the codes) runs on
+// the timeslice walk where a chunk fits; the preparation (hop input decoded
+// from codes) and small lattices on the register kernel.
 template <int SP, int SRC>
 static void launch_src(DslashArgs A, hipStream_t s)
 {
+    A.st = nullptr;  // uniform parameters
+    if constexpr (SRC == 2)
+        if (launch_walk<SP, false, EPI_PLAIN, true, 2>(A, s)) return;
     A.twalk = 1;
     A.gouter = 0;
     A.nblk_site = (A.g.vh + BLOCK - 1) / BLOCK;

@@ -197,7 +197,7 @@ static int admit(tm_server *S, Request *R)
         j.tol = sp.tol;
         j.max_iter = sp.max_iter;
         j.fixed = sp.fixed_iters;
-        j.delta = sp.delta > 0 ? sp.delta : 0.01;
+        j.delta = sp.delta > 0 ? sp.delta : TM_DEFAULT_DELTA;
         j.raw_out = raw;
         j.want_true = R->P.want_true_resid;
         j.owner = R;
@@ -458,7 +458,10 @@ extern "C" int tm_serve_submit(tm_server *S, const tm_request *req)
 extern "C" int tm_serve_poll(tm_server *S, tm_result *out, int max)
 {
     if (!S || (max > 0 && !out)) return TM_ERR_ARG;
-    std::lock_guard<std::mutex> lk(S->mu);
+    // pinned buffers are released after the lock: hipHostFree may wait for
+    // the device, and the worker must not wait for it on the lock
+    std::vector<double *> unpin;
+    std::unique_lock<std::mutex> lk(S->mu);
     int n = 0;
     while (n < max && !S->finished.empty()) {
         Request *R = S->finished.front();
@@ -496,9 +499,11 @@ extern "C" int tm_serve_poll(tm_server *S, tm_result *out, int max)
         r.t_submit = R->t_submit;
         r.t_admit = R->t_admit;
         r.t_done = R->t_done;
-        (void)hipHostFree(R->h_out);
+        unpin.push_back(R->h_out);
         delete R;
     }
+    lk.unlock();
+    for (double *h : unpin) (void)hipHostFree(h);
     return n;
 }
 

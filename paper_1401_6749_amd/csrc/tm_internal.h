@@ -14,6 +14,11 @@
 #include "tm_launch.h"
 #include "tm_types.h"
 
+// Reliable-update threshold of the mixed solver when the caller passes 0:
+// the FP32 recursion carries the residual down three orders of magnitude
+// before the FP64 true residual replaces it, four orders above FP32 rounding.
+constexpr double TM_DEFAULT_DELTA = 1e-3;
+
 struct tm_context {
     int device = 0;
     size_t budget = 0;

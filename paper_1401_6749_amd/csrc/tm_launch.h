@@ -43,6 +43,9 @@ void launch_reduce(const double *partial, int nblk, int n, double *out, hipStrea
 void launch_convert(int pin, int pout, const Geom &g, const char *in, size_t in_slot, char *out, size_t out_slot,
                     int nslot, hipStream_t s);
 void launch_zero(int p, const Geom &g, char *f, size_t slot, int nslot, hipStream_t s);
+// r = p = in (rounded to pout), x = 0 for nslot slots; r, p and x share the pitch out_slot; pin P32 or P64
+void launch_cg_start(int pin, int pout, const Geom &g, const char *in, size_t in_slot, char *r, char *p, char *x,
+                     size_t out_slot, int nslot, hipStream_t s);
 // x64 += x32; x32 = 0 (if x32_zero), n consecutive slots with strides s64, s32
 void launch_accum_x(const Geom &g, char *x64, size_t s64, const char *x32_in, char *x32_zero, size_t s32, int n,
                     hipStream_t s);

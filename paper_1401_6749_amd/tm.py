@@ -281,7 +281,7 @@ def tm_dslash_ex(ctx, gauge, op, kappa, two_kappa_mu, prec, nrhs, inp, in_stride
     _check(ctx, rc, "tm_dslash_ex")
 
 
-def solver_params(mode="f64", tol=1e-10, max_iter=100000, fixed_iters=0, half="f16", delta=0.01, chunk=0):
+def solver_params(mode="f64", tol=1e-10, max_iter=100000, fixed_iters=0, half="f16", delta=1e-3, chunk=0):
     return tm_solver_params(MODES[mode], PREC[half], float(tol), int(max_iter), int(fixed_iters), float(delta),
                             int(chunk))
 
