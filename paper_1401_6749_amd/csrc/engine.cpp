@@ -836,12 +836,26 @@ int run_jobs(std::vector<Batch *> &batches, std::vector<std::vector<Job *>> &que
         }
         if (!any) break;
         if (!progressed) {
-            // block on the first batch still in flight
-            for (Batch *b : batches)
-                if (b->in_flight) {
-                    (void)hipEventSynchronize(b->ev);
-                    break;
+            // wait for the first batch to finish its chunk, whichever it is,
+            // so that its stream is refilled while the others still run
+            int nflight = 0;
+            for (Batch *b : batches) nflight += b->in_flight ? 1 : 0;
+            if (nflight == 1) {
+                for (Batch *b : batches)
+                    if (b->in_flight) {
+                        (void)hipEventSynchronize(b->ev);
+                        break;
+                    }
+            } else if (nflight > 1) {
+                for (bool ready = false; !ready;) {
+                    for (Batch *b : batches)
+                        if (b->in_flight && hipEventQuery(b->ev) != hipErrorNotReady) {
+                            ready = true;
+                            break;
+                        }
+                    if (!ready) std::this_thread::yield();
                 }
+            }
         }
     }
     for (Batch *b : batches) (void)hipStreamSynchronize(b->stream);
