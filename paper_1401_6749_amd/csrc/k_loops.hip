@@ -92,9 +92,10 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 // of parity 0, then parity 1, each in cb order) for one source.  For FP32
 // solutions it has one wave per kind of spin matrix: the nine waves walk the
 // same sites at the same time, so the solution, the links and the codes of a
-// site come from HBM once and the other kinds hit the caches.  Each lane accumulates its sites, the wave reduces in a fixed order
-// and writes one partial per (timeslice, chunk, kind); a second kernel sums
-// the chunks of each timeslice in order and applies one complex factor.
+// site come from HBM once and the other kinds hit the caches.  Each lane
+// accumulates its sites, the wave reduces in a fixed order and writes one
+// partial per (timeslice, chunk, kind); a second kernel sums the chunks of
+// each timeslice in order and applies one complex factor.
 //   kind 0:      P_ab  = sum conj(l_a) . s_b
 //   kind 1+nu:   F_ab  = sum conj(l_a(x)) . [U_nu(x) s(x+nu)]_b
 //   kind 5+nu:   B_ab  = sum conj([U_nu(x) l(x+nu)]_a) . s_b(x)
