@@ -379,14 +379,39 @@ static void fill_noise_run(Batch *b, int s0, int n, Job *const *jobs, int pp)
     double *part = b->partial + (size_t)s0 * b->nblk;
     dsl_codes_run(b, pp, 3, CM_PREP, 0, s0, n, nullptr, 0, Be, w, kappa, a);
     dsl_run(b, pp, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, w, nullptr, 0, To, w, kappa, a, n);
-    dsl_run(b, pp, true, EPI_NORM, CM_MHAT_DAG, 0, To, w, Be, w, Ce, w, kappa, a, n, part);
+    // LP runs: the last preparation Dslash writes r = p = rhs and x = 0 in
+    // half precision itself (same bits as the FP32 rhs converted after it)
+    bool fused = false;
+    if (!mixed && pp == P32 && b->xr == b->sp && b->hxr == b->hsp && (b->xr == P16 || b->xr == PBF)) {
+        DslashArgs A = dargs(b, pp);
+        A.nslot = n;
+        A.in = To;
+        A.in_slot = w;
+        A.in2 = Be;
+        A.in2_slot = w;
+        A.out = b->p + s0 * b->hsp;
+        A.out_slot = b->hsp;
+        A.r = b->r + s0 * b->hxr;
+        A.x = b->x + s0 * b->hxr;
+        A.xr_slot = b->hxr;
+        A.out_par = 0;
+        A.coef = CM_MHAT_DAG;
+        A.kappa_u = kappa;
+        A.a_u = a;
+        A.partial = part;
+        fused = launch_dslash_start(b->xr, A, s) == 0;
+    }
+    if (!fused) dsl_run(b, pp, true, EPI_NORM, CM_MHAT_DAG, 0, To, w, Be, w, Ce, w, kappa, a, n, part);
     launch_slot_start(b->st + s0, part, b->nblk, P, n, s);
-    if (b->xr == b->sp && b->hxr == b->hsp) {
-        launch_cg_start(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->p + s0 * b->hsp, b->x + s0 * b->hxr, b->hxr, n, s);
-    } else {
-        launch_convert(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->hxr, n, s);
-        launch_convert(pp, b->sp, g, Ce, w, b->p + s0 * b->hsp, b->hsp, n, s);
-        launch_zero(b->xr, g, b->x + s0 * b->hxr, b->hxr, n, s);
+    if (!fused) {
+        if (b->xr == b->sp && b->hxr == b->hsp) {
+            launch_cg_start(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->p + s0 * b->hsp, b->x + s0 * b->hxr, b->hxr,
+                            n, s);
+        } else {
+            launch_convert(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->hxr, n, s);
+            launch_convert(pp, b->sp, g, Ce, w, b->p + s0 * b->hsp, b->hsp, n, s);
+            launch_zero(b->xr, g, b->x + s0 * b->hxr, b->hxr, n, s);
+        }
     }
     if (mixed) {
         launch_convert(P64, P64, g, Ce, w, b->b64 + s0 * b->h64, b->h64, n, s);

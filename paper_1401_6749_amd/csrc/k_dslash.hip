@@ -465,7 +465,7 @@ constexpr int dslash_waves()
 // Site-local epilogue of output site cb of slot: out = P in2 + Q hop with the
 // CG update / residual variants; returns the site's contribution to the
 // slot's reduction (0 for EPI_PLAIN).
-template <int SP, int EPI, bool IN2, int SRC, bool NT = false>
+template <int SP, int EPI, bool IN2, int SRC, bool NT = false, int PO = SP>
 __device__ __forceinline__ double epilogue(const DslashArgs &A, int slot, int cb, const cpx<typename Real<SP>::T> acc[12],
                                            double kappa, double a, double alpha)
 {
@@ -515,6 +515,21 @@ __device__ __forceinline__ double epilogue(const DslashArgs &A, int slot, int cb
         }
         SpinorIO<XR>::store(xs, vh, cb, x);
         SpinorIO<XR>::store(rs, vh, cb, rr);
+    } else if (EPI == EPI_START) {
+        // start of a CG solve: r = p = v and x = 0 in the CG storage
+        // precision PO, each rounded from the FP64 widening of v exactly as a
+        // separate conversion of the stored FP32 v rounds it; the norm is
+        // that of v, as EPI_NORM forms it
+        cpx<double> vd[12], zd[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            vd[k] = cpx<double>{(double)v[k].re, (double)v[k].im};
+            zd[k] = cpx<double>{0.0, 0.0};
+            part += (double)norm2(v[k]);
+        }
+        SpinorIO<PO>::template store<double, NT>(A.r + (size_t)slot * A.xr_slot, vh, cb, vd);
+        SpinorIO<PO>::template store<double, NT>(A.out + (size_t)slot * A.out_slot, vh, cb, vd);
+        SpinorIO<PO>::template store<double, NT>(A.x + (size_t)slot * A.xr_slot, vh, cb, zd);
     } else {  // EPI_RESID (FP64 only)
         cpx<T> b[12];
         SpinorIO<P64>::load(A.b + (size_t)slot * A.b_slot, vh, cb, b);
@@ -777,7 +792,7 @@ constexpr int walk_waves()
 
 // SRC bit 1: the site-local input is eta decoded from Z4 codes (the
 // reconstruction of noise solves), as in k_dslash.
-template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, bool NT, int SRC = 0>
+template <int SP, bool DAG, int EPI, bool IN2, bool SLOT, bool NT, int SRC = 0, int PO = SP>
 __global__ __launch_bounds__(walk_max<SP>(), (walk_waves<SP, EPI>())) void k_dslash_walk(const DslashArgs A)
 {
     using T = typename Real<SP>::T;
@@ -863,7 +878,7 @@ __global__ __launch_bounds__(walk_max<SP>(), (walk_waves<SP, EPI>())) void k_dsl
         // next timeslice's halo, while its owners are reading it
         if constexpr (PF != 0)
             if (k + 1 < tw) halo_load(t + 1);
-        const double part = epilogue<SP, EPI, IN2, SRC, NT>(A, slot, cb, acc, kappa, a, alpha);
+        const double part = epilogue<SP, EPI, IN2, SRC, NT, PO>(A, slot, cb, acc, kappa, a, alpha);
         if constexpr (EPI != EPI_PLAIN) {
             // one wave = one 64-site reduction tile
             const double v = wave_sum(part);
@@ -946,7 +961,7 @@ inline int lds_twalk()
     return tw;
 }
 
-template <int SP, bool DAG, int EPI, bool IN2, int SRC = 0>
+template <int SP, bool DAG, int EPI, bool IN2, int SRC = 0, int PO = SP>
 static bool launch_walk(DslashArgs A, hipStream_t s)
 {
     {
@@ -966,8 +981,9 @@ static bool launch_walk(DslashArgs A, hipStream_t s)
         const int total = A.nblk_site * A.nslot;
         const int grid = A.swz ? 8 * ((total + 7) / 8) : total;
         // outputs are streamed past L2 (non-temporal), keeping it for the halo lines
-        if constexpr (SRC != 0)
-            hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, false, true, SRC>), dim3(grid), dim3(cs), 0, s, A);
+        if constexpr (SRC != 0 || PO != SP)
+            hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, false, true, SRC, PO>), dim3(grid), dim3(cs), 0, s,
+                               A);
         else if (A.st)
             hipLaunchKernelGGL((k_dslash_walk<SP, DAG, EPI, IN2, true, true>), dim3(grid), dim3(cs), 0, s, A);
         else
@@ -1048,6 +1064,17 @@ int launch_dslash_codes(int sp, int src, const DslashArgs &A, hipStream_t s)
     else if (src == 2) sp == P64 ? launch_src<P64, 2>(A, s) : launch_src<P32, 2>(A, s);
     else return -1;
     return 0;
+}
+
+int launch_dslash_start(int po, const DslashArgs &A, hipStream_t s)
+{
+    if (A.nslot < 1) return 0;
+    DslashArgs B = A;
+    B.st = nullptr;  // uniform parameters
+    bool ok = false;
+    if (po == P16) ok = launch_walk<P32, true, EPI_START, true, 0, P16>(B, s);
+    else if (po == PBF) ok = launch_walk<P32, true, EPI_START, true, 0, PBF>(B, s);
+    return ok ? 0 : -1;
 }
 
 int launch_dslash(int sp, bool dag, int epi, bool in2, const DslashArgs &A, hipStream_t s)

@@ -104,7 +104,8 @@ enum : int {
     EPI_PLAIN = 0,  // out = P in2 + Q hop
     EPI_NORM = 1,   // as PLAIN, plus per-block |out|^2
     EPI_CGUPD = 2,  // Ap = P in2 + Q hop; x += alpha p; r -= alpha Ap; per-block |r|^2
-    EPI_RESID = 3   // out = b - (P in2 + Q hop); per-block |out|^2
+    EPI_RESID = 3,  // out = b - (P in2 + Q hop); per-block |out|^2
+    EPI_START = 4   // v = P in2 + Q hop; r = out = v and x = 0 in the CG storage precision; per-block |v|^2
 };
 
 constexpr int MAX_SLOTS = 16;
