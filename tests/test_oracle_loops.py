@@ -202,3 +202,76 @@ def test_table1_efficiency_consistency():
             prod = rows["R_C"][k] * rows["R_E_" + obs][k] ** 2
             printed = rows["RCRE2_" + obs][k]
             assert abs(prod - printed) <= 0.006 + 0.02 * printed
+
+
+def _direct_derivative_loops(dims, tbc, U, Minv, G):
+    """L^D_{G,nu}(t) written straight from the symmetric covariant derivative
+    of the bilinear, attributed to x (the reading of the one-derivative
+    operators; the abstract's "up to one derivative", Fig. 1's i psibar g3 D3 psi):
+      1/4 [ psibar(x) G U_nu(x) psi(x+nu)      - psibar(x) G U_nu(x-nu)^dag psi(x-nu)
+          - psibar(x+nu) G U_nu(x)^dag psi(x) + psibar(x-nu) G U_nu(x-nu) psi(x) ],
+    each bilinear psibar(y) A psi(z) traced as Tr[A Minv(z, y)] (raw normalisation,
+    no fermion-loop sign), summed over the sites x of timeslice t.  Every hop that
+    crosses the time boundary carries tbc.  Returns (4, T) for nu = x, y, z, t."""
+    V = int(np.prod(dims))
+    T = dims[3]
+    blk = lambda z, y: Minv[12 * z:12 * z + 12, 12 * y:12 * y + 12]
+    out = np.zeros((4, T), dtype=np.complex128)
+    for x in range(V):
+        t = H.coords(dims, x)[3]
+        for nu in range(4):
+            f, sf = H.shifted(dims, x, nu, +1, tbc)  # x + nu and the sign of that hop
+            b, sb = H.shifted(dims, x, nu, -1, tbc)  # x - nu
+            Uf = sf * U[x, nu]                        # U_nu(x), boundary sign folded in
+            Ub = sb * U[b, nu]                        # U_nu(x - nu)
+            tr = lambda A, z, y: np.trace(A @ blk(z, y))
+            k = lambda A: np.kron(G, A)
+            t1 = tr(k(Uf), f, x)
+            t2 = tr(k(Ub.conj().T), b, x)
+            t3 = tr(k(Uf.conj().T), x, f)
+            t4 = tr(k(Ub), x, b)
+            out[nu, t] += 0.25 * (t1 - t2 - t3 + t4)
+    return out
+
+
+@pytest.mark.parametrize("tbc", [-1, 1])
+def test_derivative_projection_matches_covariant_definition(oracle, tbc):
+    """The projection's one-derivative loops (ops 16..79, the time shift
+    included) and the symmetrised O_mu_nu (ops 80..89), applied to the
+    full-dilution spin matrices of the contraction, equal the four-term
+    symmetric covariant derivative written out site by site from the dense
+    inverse.  The field is random, so F(t-1) and F(t+1) differ and a shift in
+    the wrong direction fails."""
+    dims = (2, 2, 2, 6)
+    V = int(np.prod(dims))
+    U = inputs.gauge_field(dims, seed=171 + tbc)
+    kappa, a = 0.13, 0.04
+    M = H.dense_from_apply(lambda e: oracle.apply_M(dims, tbc, U, kappa, a, e), 12 * V)
+    Minv = np.linalg.inv(M)
+    acc = np.zeros((9, dims[3], 4, 4), dtype=np.complex128)
+    for j in range(12 * V):
+        e = np.zeros(12 * V, dtype=np.complex128)
+        e[j] = 1
+        acc += oracle.contract(dims, tbc, U, e, Minv[:, j])
+    ops = oracle.project(acc)
+    G16 = [np.eye(4, dtype=complex)] + H.GAMMAS + [H.G5] + [g @ H.G5 for g in H.GAMMAS]
+    for m in range(4):
+        for n in range(m + 1, 4):
+            G16.append(0.5j * (H.GAMMAS[m] @ H.GAMMAS[n] - H.GAMMAS[n] @ H.GAMMAS[m]))
+    direct = np.array([_direct_derivative_loops(dims, tbc, U, Minv, G) for G in G16])  # (16, 4, T)
+    scale = np.abs(direct).max()
+    for gi in range(16):
+        for nu in range(4):
+            got = ops[16 + 4 * gi + nu]
+            assert np.allclose(got, direct[gi, nu], rtol=0, atol=1e-12 * scale), (gi, nu)
+    for i, (m, n) in enumerate(oracle.SYM_PAIRS):
+        want = 0.5 * (direct[1 + m, n] + direct[1 + n, m])
+        assert np.allclose(ops[80 + i], want, rtol=0, atol=1e-12 * scale), (m, n)
+    # the time shift is visible on this field: the temporal F and B of the
+    # vector insertions are not constant in t, so rolling the other way would
+    # change ops 16 + 4 g + 3 by far more than the tolerance
+    proj = np.einsum("gab,ktab->gkt", np.array(G16), acc)
+    for gi in (1, 2, 3, 4):
+        F, B = proj[gi, 4], proj[gi, 8]
+        wrong = 0.25 * (F + np.roll(F, -1) - B - np.roll(B, -1))
+        assert np.abs(wrong - direct[gi, 3]).max() > 1e-6 * scale
