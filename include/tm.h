@@ -86,7 +86,8 @@ typedef enum tm_op {
 typedef enum tm_solve_mode {
     TM_SOLVE_F64 = 0,   /* plain FP64 CG throughout */
     TM_SOLVE_MIXED = 1, /* FP32 CG with FP64 reliable updates of x and the true residual */
-    TM_SOLVE_LP = 2     /* half-precision (F16 or BF16) operands, FP32 x and r, FP32 math */
+    TM_SOLVE_LP = 2     /* every CG vector (p, the Dslash intermediates, x and r) stored in F16 or
+                           BF16 with an FP32 per-site scale; FP32 arithmetic, FP64 global sums */
 } tm_solve_mode;
 
 /* Device allocator used for every library allocation.  NULL means hipMalloc
@@ -125,10 +126,12 @@ int tm_memory_usage(const tm_context *ctx, size_t *in_use, size_t *peak);
  *   links_host  host, canonical gauge layout, V*4*9 complex doubles
  *   t_bc        -1 antiperiodic or +1 periodic in time
  * Every link is checked for unitarity and det = 1 (|U^dag U - 1| and
- * |det U - 1| below 1e-10); links are stored as their first two rows.
+ * |det U - 1| below 1e-10).  The kernels address a link array through
+ * 32-bit buffer offsets, so the FP64 copy (384 bytes per site) must stay
+ * below 4 GiB: at most 11184810 sites (48^3 x 96 fits, 64^4 does not).
  * The caller keeps links_host; the library owns the device copies until
- * tm_free_gauge.  Synchronous.  Errors: TM_ERR_ARG (dims, t_bc, non-SU(3)
- * link, NaN), TM_ERR_NOMEM, TM_ERR_HIP. */
+ * tm_free_gauge.  Synchronous.  Errors: TM_ERR_ARG (dims, too many sites,
+ * t_bc, non-SU(3) link, NaN), TM_ERR_NOMEM, TM_ERR_HIP. */
 int tm_load_gauge(tm_context *ctx, const int dims[4], const double *links_host, int t_bc,
                   unsigned prec_mask, tm_gauge **out);
 

@@ -224,6 +224,17 @@ static bool dims_ok(const int *d)
     return v <= (1ll << 30);
 }
 
+// The kernels reach a link array and a spinor field through buffer resources
+// with 32-bit byte offsets.  The largest array is the FP64 link copy, 2
+// parities x 4 directions x 96 bytes per even-odd site = 384 bytes per site,
+// so a lattice fits when 384 V stays below 4 GiB (every spinor field, at most
+// 192 bytes per site of a parity, then fits too).
+static bool lattice_fits(const int *d)
+{
+    const unsigned long long v = (unsigned long long)d[0] * d[1] * d[2] * d[3];
+    return v * 384ull <= 0xFFFFFFFFull;
+}
+
 // max over links of |U^dag U - 1| and |det U - 1|; NaN-aware
 static double su3_violation(const double *links, size_t nlinks)
 {
@@ -262,6 +273,10 @@ extern "C" int tm_load_gauge(tm_context *ctx, const int dims[4], const double *l
     if (!out || !links_host) return set_err(ctx, TM_ERR_ARG, "null argument");
     *out = nullptr;
     if (!dims_ok(dims)) return set_err(ctx, TM_ERR_ARG, "lattice extents must be even and >= 2");
+    if (!lattice_fits(dims))
+        return set_err(ctx, TM_ERR_ARG,
+                       "lattice too large: its FP64 link array would exceed the 4 GiB that 32-bit buffer offsets "
+                       "address (at most %llu sites)", 0xFFFFFFFFull / 384ull);
     if (t_bc != 1 && t_bc != -1) return set_err(ctx, TM_ERR_ARG, "t_bc must be +1 or -1");
     if (prec_mask & ~15u) return set_err(ctx, TM_ERR_ARG, "unknown precision bits 0x%x", prec_mask);
     const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
@@ -986,6 +1001,13 @@ extern "C" int tm_selftest(void)
     int dims[4] = {6, 4, 2, 8};
     Geom g = make_geom(dims, -1);
     if (g.vh != 6 * 4 * 2 * 8 / 2 || g.v3h * dims[3] != g.vh || g.st != g.v3h) return 3;
+    // lattice size limit of the 32-bit buffer offsets
+    {
+        const int fit[3][4] = {{32, 32, 32, 64}, {48, 48, 48, 96}, {2, 2, 2, 2}};
+        const int big[3][4] = {{64, 64, 64, 64}, {56, 56, 56, 64}, {1024, 1024, 16, 2}};
+        for (int k = 0; k < 3; k++)
+            if (!lattice_fits(fit[k]) || lattice_fits(big[k])) return 9;
+    }
     // arena: random allocations and releases keep blocks disjoint, in range,
     // aligned, and coalesce back to one free block
     {

@@ -70,3 +70,26 @@ def apply_op(g, op, kappa, a, prec, psi, dims):
 
 def relerr(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+# operator classes of the 90 projected loops: 16 local, 64 one-derivative
+# L^D_{G,nu}, 10 symmetrised g_mu D_nu
+OP_CLASSES = {"local": slice(0, 16), "deriv": slice(16, 80), "sym": slice(80, 90)}
+
+
+def op_class_errors(raw_test, raw_ref, oracle):
+    """Relative error ||L_test - L_ref|| / ||L_ref|| per operator class, over
+    the class's operators and all timeslices, of the loops projected (by the
+    oracle) from spin matrices (9, T, 4, 4)."""
+    a = oracle.project(np.asarray(raw_test))
+    b = oracle.project(np.asarray(raw_ref))
+    return {k: relerr(a[s], b[s]) for k, s in OP_CLASSES.items()}
+
+
+def assert_classes(raw_test, raw_ref, oracle, tol, what=""):
+    """Every operator class within tol (a whole small class cannot hide in
+    the norm of the larger ones)."""
+    e = op_class_errors(raw_test, raw_ref, oracle)
+    for k, v in e.items():
+        assert v < tol, (what, k, v, e)
+    return e

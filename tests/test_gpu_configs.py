@@ -30,3 +30,37 @@ def test_c2_plain_f64_16c32(oracle):
     assert GU.relerr(r["est"], ops.mean(axis=0)) < 1e-12
     assert r["stats"]["lp_solves"] == 64
     tm.tm_free_gauge(ctx, g)
+
+
+def test_c3_tsm_24c48(oracle):
+    """TSM with precision at 24^3x48 (kappa 0.1636, 2 kappa mu 0.0033, gauge
+    seed 3, noise seed 103): the bench's launch shape (12 right-hand sides per
+    batch) with mixed-precision HP solves to 1e-10 and LP solves at a fixed
+    five iterations.  Sampled sources against the oracle: the mixed HP loops
+    within the two solves' 1e-10 stopping (both converge to the same
+    solution), the FP64 LP path to 1e-10 and the FP16 LP path within its
+    storage rounding, per operator class."""
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (24, 24, 24, 48)
+    U = inputs.gauge_field(dims, seed=3)
+    g = GU.load(dims, U)
+    kappa, a, seed = 0.1636, 0.0033, 103
+    lt = dims[3]
+    ids = [0, 11]
+    ref = oracle.loops_tsm(dims, -1, U, kappa, a, seed, 2, 10, hp_tol=1e-10, lp_fixed_iters=5, source_ids=ids,
+                           return_raw=True)
+    P16 = tm.tsm_params(kappa, a, seed, 2, 10, hp=tm.solver_params("mixed", tol=1e-10),
+                        lp=tm.solver_params("lp", fixed_iters=5, half="f16"), batch=12, want_true_resid=1)
+    r16 = tm.tm_loops_tsm(ctx, g, P16, lt, want_raw=True)
+    P64 = tm.tsm_params(kappa, a, seed, 0, 12, lp=tm.solver_params("f64", fixed_iters=5), batch=12)
+    r64 = tm.tm_loops_tsm(ctx, g, P64, lt, want_raw=True)
+    assert GU.relerr(r16["raw_hp"][0], ref["hp_raw"][0]) < 1e-8
+    GU.assert_classes(r16["raw_hp"][0], ref["hp_raw"][0], oracle, 1e-8, "hp")
+    assert r16["stats"]["max_hp_true_resid"] < 1e-8
+    for j in ids:
+        assert GU.relerr(r64["raw_lp"][j], ref["lp_raw"][j]) < 1e-10, j
+        GU.assert_classes(r16["raw_lp"][j], ref["lp_raw"][j], oracle, 5e-3, ("lp f16", j))
+    assert np.all(np.isfinite(r16["est"]))
+    tm.tm_free_gauge(ctx, g)

@@ -93,8 +93,9 @@ def test_fullsize_z4_codes(oracle):
 
 def test_fullsize_loops_matched_iterations(oracle, big):
     """Loop spin matrices of sampled sources at 32^3x64, five CG iterations
-    each: the FP64 path to 1e-10 of the oracle; the FP16 LP path (12 sources
-    in one batch, the bench's launch shape) within its storage rounding."""
+    each: the FP64 path to 1e-10 of the oracle; the FP16 and BF16 LP paths
+    (12 sources in one batch, the bench's launch shape) within their storage
+    rounding, for every operator class (local, one-derivative, symmetrised)."""
     from paper_1401_6749_amd import tm
 
     U, g = big
@@ -104,11 +105,14 @@ def test_fullsize_loops_matched_iterations(oracle, big):
                            return_raw=True)
     P64 = tm.tsm_params(KAPPA, A, 104, 0, 12, lp=tm.solver_params("f64", fixed_iters=5), batch=12)
     r64 = tm.tm_loops_tsm(ctx, g, P64, lt, want_raw=True)
-    P16 = tm.tsm_params(KAPPA, A, 104, 0, 12, lp=tm.solver_params("lp", fixed_iters=5, half="f16"), batch=12)
-    r16 = tm.tm_loops_tsm(ctx, g, P16, lt, want_raw=True)
     for j in (0, 11):
         assert GU.relerr(r64["raw_lp"][j], ref["lp_raw"][j]) < 1e-10, j
-        assert GU.relerr(r16["raw_lp"][j], ref["lp_raw"][j]) < 5e-3, j
+    for half, tol in (("f16", 5e-3), ("bf16", 3e-2)):
+        P = tm.tsm_params(KAPPA, A, 104, 0, 12, lp=tm.solver_params("lp", fixed_iters=5, half=half), batch=12)
+        r = tm.tm_loops_tsm(ctx, g, P, lt, want_raw=True)
+        for j in (0, 11):
+            assert GU.relerr(r["raw_lp"][j], ref["lp_raw"][j]) < tol, (half, j)
+            GU.assert_classes(r["raw_lp"][j], ref["lp_raw"][j], oracle, tol, (half, j))
 
 
 def test_fullsize_loops_oet_f64(oracle, big):

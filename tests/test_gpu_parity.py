@@ -245,6 +245,7 @@ def test_lp_noise_path_matched_iterations(oracle, half):
     tol = 5e-3 if half == "f16" else 3e-2
     for j in range(3):
         assert GU.relerr(r["raw_lp"][j], ref["lp_raw"][j]) < tol, (j, GU.relerr(r["raw_lp"][j], ref["lp_raw"][j]))
+        GU.assert_classes(r["raw_lp"][j], ref["lp_raw"][j], oracle, tol, (half, j))
     assert r["stats"]["lp_iters"] == 15
 
 
@@ -317,6 +318,15 @@ def test_loops_oet_lp_matched_iterations(oracle, half, tol):
         for j in (0, 7):
             assert GU.relerr(out[0][f"raw_{f}_lp"][j], ref["raw"]["lp_" + f][j]) < tol, (f, j)
         assert np.array_equal(out[0][f"raw_{f}_lp"], out[1][f"raw_{f}_lp"]), f
+    # per operator class, with the flavour's insertions (g5 G and g5 G g5)
+    G = oracle.gammas16()
+    g5 = oracle.gamma(4)
+    for f, gam in (("vv", np.array([g5 @ x for x in G])), ("ws", np.array([g5 @ x @ g5 for x in G]))):
+        for j in (0, 7):
+            a = oracle.project(out[0][f"raw_{f}_lp"][j], gam)
+            b = oracle.project(ref["raw"]["lp_" + f][j], gam)
+            for k, sl in GU.OP_CLASSES.items():
+                assert GU.relerr(a[sl], b[sl]) < tol, (f, j, k)
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-14), ("f32", 2e-6), ("f16", 3e-3)])

@@ -36,7 +36,8 @@ def test_serving_alone_equals_in_mix(oracle):
     dA, dB = (8, 8, 8, 16), (4, 4, 4, 8)
     gA = GU.load(dA, inputs.gauge_field(dA, 11))
     gA2 = GU.load(dA, inputs.gauge_field(dA, 12))
-    gB = GU.load(dB, inputs.gauge_field(dB, 13))
+    UB = inputs.gauge_field(dB, 13)
+    gB = GU.load(dB, UB)
     PA = _req_params(tm, 0.1636, 0.0033, 7, 3, 20)
     srv = tm.tm_serve_create(ctx, slots=12, workspace_budget=1 << 30)
     try:
@@ -45,13 +46,28 @@ def test_serving_alone_equals_in_mix(oracle):
         assert alone["status"] == 0
         # the same request inside a mix of other lattices, gauge fields, masses
         # and precisions, submitted together so their sources share launches
+        # an FP64 request (HP to 1e-10, LP truncated at 1e-2, both in FP64):
+        # its result has an oracle reference
+        P64 = tm.tsm_params(0.12, 0.02, 31, 2, 5, hp=tm.solver_params("f64", tol=1e-10),
+                            lp=tm.solver_params("f64", tol=1e-2))
         mix = [(gA2, _req_params(tm, 0.1636, 0.01, 8, 2, 15)),
                (gB, _req_params(tm, 0.12, 0.0033, 9, 4, 30, half="bf16")),
                (gA, _req_params(tm, 0.13, 0.01, 10, 1, 12)),
-               (gA, PA)]
+               (gA, PA),
+               (gB, P64)]
         for k, (g, P) in enumerate(mix):
             assert tm.tm_serve_submit(srv, g, P, 100 + k) == 0
         res = _wait_all(tm, srv, len(mix))
+        # the FP64 request against the oracle's whole path (Sec. 2.1, Eq. estiTSM)
+        r64 = res[104]
+        assert r64["status"] == 0
+        ref = oracle.loops_tsm(dB, -1, UB, 0.12, 0.02, 31, 2, 5, hp_tol=1e-10, lp_tol=1e-2)
+        assert GU.relerr(r64["est"], ref["est"]) < 1e-10
+        for k, sl in GU.OP_CLASSES.items():
+            assert GU.relerr(r64["est"][sl], ref["est"][sl]) < 1e-10, k
+        for key in ("var_re", "var_im"):
+            assert np.allclose(r64[key], ref[key], rtol=1e-8, atol=1e-14 * np.abs(ref[key]).max()), key
+        assert r64["stats"]["hp_solves"] == 2 and r64["stats"]["lp_solves"] == 7
         inmix = res[103]
         assert inmix["status"] == 0
         assert np.array_equal(inmix["est"], alone["est"])
