@@ -174,6 +174,23 @@ int tm_dslash_ex(tm_context *ctx, const tm_gauge *gauge, tm_op op, double kappa,
                  tm_prec prec, int nrhs, const void *in, size_t in_stride, void *out, size_t out_stride,
                  void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operators, arguments, layouts and results as tm_dslash_ex (bit for bit),
+ * without any device allocation.  The temporaries of the MHAT family (one
+ * even-odd half field per right-hand side, two for MHAT_DAG_MHAT; none for
+ * HOP, M, MDAG and BH) come from a fixed array of TM_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device it runs on until the process ends.
+ * All calls on one device share that array: calls that overlap in time on
+ * one device (other streams, other host threads) race and must be ordered by
+ * the caller.  Asynchronous on hip_stream.  Errors: as tm_dslash_ex, and
+ * TM_ERR_ARG when the temporaries exceed the array (MHAT, MHAT_DAG: nrhs
+ * half fields of prec; MHAT_DAG_MHAT: twice that). */
+#define TM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int tm_dslash_noalloc(tm_context *ctx, const tm_gauge *gauge, tm_op op, double kappa, double two_kappa_mu,
+                      tm_prec prec, int nrhs, const void *in, size_t in_stride, void *out, size_t out_stride,
+                      void *hip_stream);
+
 /* ------------------------------------------------------------------ */
 /* Solver (Sec. 2.1: "the inverter, a CG solver")                       */
 /* ------------------------------------------------------------------ */

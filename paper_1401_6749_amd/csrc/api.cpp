@@ -80,6 +80,44 @@ double now_s()
 using namespace tmi;
 
 // ---------------------------------------------------------------------------
+// Fixed device scratch of tm_dslash_noalloc: one array per device, allocated
+// with the library's code object when it is loaded on that device and held
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it only stands in for the symbol): tm_create looks up
+// its device address once per device, with that device current, and the
+// entry point uses that address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[TM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex scratch_mu;
+std::unordered_map<int, void *> scratch_addr;  // device -> address of its scratch
+
+// address of the device's scratch, looked up on first use (device current)
+int scratch_setup(int device, void **out)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    auto it = scratch_addr.find(device);
+    if (it != scratch_addr.end()) {
+        *out = it->second;
+        return TM_OK;
+    }
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TM_ERR_HIP;
+    scratch_addr[device] = p;
+    *out = p;
+    return TM_OK;
+}
+
+void *scratch_of(int device)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    auto it = scratch_addr.find(device);
+    return it == scratch_addr.end() ? nullptr : it->second;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // gamma table for the projection (chiral basis; each of the 16 insertions has
 // exactly one non-zero entry per row, valued 1, i, -1 or -i)
 // ---------------------------------------------------------------------------
@@ -174,6 +212,8 @@ extern "C" int tm_create(int device, size_t hbm_budget, tm_alloc_fn alloc, tm_fr
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return TM_ERR_ARG;
     if ((alloc == nullptr) != (free_fn == nullptr)) return TM_ERR_ARG;
     if (hipSetDevice(device) != hipSuccess) return TM_ERR_HIP;
+    void *scr = nullptr;
+    if (scratch_setup(device, &scr) != TM_OK) return TM_ERR_HIP;
     tm_context *c = new tm_context();
     c->device = device;
     c->budget = hbm_budget;
@@ -395,9 +435,43 @@ extern "C" int tm_dslash(tm_context *ctx, const tm_gauge *G, tm_op op, double ka
     return tm_dslash_ex(ctx, G, op, kappa, a, prec, nrhs, in, fb, out, fb, hip_stream);
 }
 
+// Temporaries of the MHAT family: bytes needed (0 for full-lattice operators).
+static size_t dslash_tmp_bytes(const tm_gauge *G, int p, tm_op op, int nrhs)
+{
+    const size_t hb = half_bytes(p, G->g);
+    if (op == TM_OP_MHAT || op == TM_OP_MHAT_DAG) return hb * nrhs;
+    if (op == TM_OP_MHAT_DAG_MHAT) return 2 * hb * nrhs;
+    return 0;
+}
+
+// tm_dslash_ex with its temporaries given: tmp (device) of at least
+// dslash_tmp_bytes(), or nullptr to take them from the context's scratch,
+// grown on demand.
+static int dslash_impl(tm_context *ctx, const tm_gauge *G, tm_op op, double kappa, double a, tm_prec prec, int nrhs,
+                       const void *in, size_t in_stride, void *out, size_t out_stride, void *hip_stream, char *tmp,
+                       size_t tmp_cap);
+
 extern "C" int tm_dslash_ex(tm_context *ctx, const tm_gauge *G, tm_op op, double kappa, double a, tm_prec prec,
                             int nrhs, const void *in, size_t in_stride, void *out, size_t out_stride,
                             void *hip_stream)
+{
+    return dslash_impl(ctx, G, op, kappa, a, prec, nrhs, in, in_stride, out, out_stride, hip_stream, nullptr, 0);
+}
+
+extern "C" int tm_dslash_noalloc(tm_context *ctx, const tm_gauge *G, tm_op op, double kappa, double a,
+                                 tm_prec prec, int nrhs, const void *in, size_t in_stride, void *out,
+                                 size_t out_stride, void *hip_stream)
+{
+    if (!ctx) return TM_ERR_ARG;
+    char *tmp = (char *)scratch_of(ctx->device);
+    if (!tmp) return set_err(ctx, TM_ERR_HIP, "tm_dslash_noalloc: no scratch address for device %d", ctx->device);
+    return dslash_impl(ctx, G, op, kappa, a, prec, nrhs, in, in_stride, out, out_stride, hip_stream, tmp,
+                       TM_NOALLOC_SCRATCH_BYTES);
+}
+
+static int dslash_impl(tm_context *ctx, const tm_gauge *G, tm_op op, double kappa, double a, tm_prec prec, int nrhs,
+                       const void *in, size_t in_stride, void *out, size_t out_stride, void *hip_stream, char *tmp,
+                       size_t tmp_cap)
 {
     if (!ctx) return TM_ERR_ARG;
     const int p = prec_index(prec);
@@ -442,15 +516,24 @@ extern "C" int tm_dslash_ex(tm_context *ctx, const tm_gauge *G, tm_op op, double
         }
     } else {
         // temporaries: odd half per rhs, plus an even half per rhs for MHAT_DAG_MHAT
-        const size_t need = 2 * hb * nrhs;
-        if (ctx->op_tmp_bytes < need) {
-            (void)hipDeviceSynchronize();
-            dfree(ctx, ctx->op_tmp);
-            ctx->op_tmp = dalloc(ctx, need);
-            ctx->op_tmp_bytes = ctx->op_tmp ? need : 0;
-            if (!ctx->op_tmp) return set_err(ctx, TM_ERR_NOMEM, "tm_dslash: no memory for temporaries");
+        const size_t need = dslash_tmp_bytes(G, p, op, nrhs);
+        if (tmp) {
+            if (need > tmp_cap)
+                return set_err(ctx, TM_ERR_ARG,
+                               "tm_dslash_noalloc: the operator needs %zu bytes of temporaries, the fixed scratch "
+                               "holds %zu", need, tmp_cap);
+        } else {
+            const size_t grow = 2 * hb * nrhs;
+            if (ctx->op_tmp_bytes < grow) {
+                (void)hipDeviceSynchronize();
+                dfree(ctx, ctx->op_tmp);
+                ctx->op_tmp = dalloc(ctx, grow);
+                ctx->op_tmp_bytes = ctx->op_tmp ? grow : 0;
+                if (!ctx->op_tmp) return set_err(ctx, TM_ERR_NOMEM, "tm_dslash: no memory for temporaries");
+            }
+            tmp = (char *)ctx->op_tmp;
         }
-        char *t = (char *)ctx->op_tmp, *u = t + hb * nrhs;
+        char *t = tmp, *u = t + hb * nrhs;
         auto mhat = [&](const char *src, size_t src_stride, char *dst, size_t dst_stride, bool dag) {
             A.in_slot = src_stride;
             A.out_slot = hb;

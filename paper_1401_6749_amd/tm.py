@@ -117,6 +117,8 @@ _sig = {
     "tm_dslash": (c_int, [c_void_p, c_void_p, c_int, c_double, c_double, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "tm_dslash_ex": (c_int, [c_void_p, c_void_p, c_int, c_double, c_double, c_int, c_int, c_void_p, c_size_t,
                              c_void_p, c_size_t, c_void_p]),
+    "tm_dslash_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_double, c_double, c_int, c_int, c_void_p, c_size_t,
+                                  c_void_p, c_size_t, c_void_p]),
     "tm_cg_solve": (c_int, [c_void_p, c_void_p, c_double, c_double, ctypes.POINTER(tm_solver_params), c_int,
                             c_void_p, c_void_p, ctypes.POINTER(tm_solve_stats), c_void_p]),
     "tm_z4_source": (c_int, [c_void_p, ctypes.POINTER(c_int), c_uint64, c_uint64, c_void_p, c_void_p]),
@@ -279,6 +281,16 @@ def tm_dslash_ex(ctx, gauge, op, kappa, two_kappa_mu, prec, nrhs, inp, in_stride
                            float(two_kappa_mu), PREC[prec], int(nrhs), _ptr(inp), int(in_stride), _ptr(out),
                            int(out_stride), _stream(stream))
     _check(ctx, rc, "tm_dslash_ex")
+
+
+def tm_dslash_noalloc(ctx, gauge, op, kappa, two_kappa_mu, prec, nrhs, inp, in_stride, out, out_stride, stream=None,
+                      check=True):
+    rc = _lib.tm_dslash_noalloc(ctx, gauge, OPS[op] if isinstance(op, str) else int(op), float(kappa),
+                                float(two_kappa_mu), PREC[prec], int(nrhs), _ptr(inp), int(in_stride), _ptr(out),
+                                int(out_stride), _stream(stream))
+    if check:
+        _check(ctx, rc, "tm_dslash_noalloc")
+    return rc
 
 
 def solver_params(mode="f64", tol=1e-10, max_iter=100000, fixed_iters=0, half="f16", delta=1e-3, chunk=0):
