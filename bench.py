@@ -37,9 +37,19 @@ WORKLOADS = {
                               batch=12, gauge_seed=4, noise_seed=104),
     "tsm-24c48": dict(dims=(24, 24, 24, 48), kappa=0.1636, a=0.0033, n_hp=24, n_lp=500, half="f16", batch=12,
                       gauge_seed=3, noise_seed=103),
+    # the plain method in FP64 at 16^3x32 (64 sources to 1e-10): a segment of the default run
+    "plain-16c32": dict(dims=(16, 16, 16, 32), kappa=0.12, a=0.005, n_hp=0, n_lp=64, half="f16", batch=12,
+                        gauge_seed=2, noise_seed=102),
 }
-LINK_BYTES = {"f64": 96, "f32": 48, "f16": 36, "bf16": 36}
+# Algorithmic bytes (what the method must move): every link as 12 reals
+# (two rows; the third follows from unitarity), half-precision spinors with
+# their FP32 per-site scale.  The library stores half-precision links with all
+# nine entries (36 B); that storage figure is reported beside the algorithmic one.
+LINK_BYTES = {"f64": 96, "f32": 48, "f16": 24, "bf16": 24}
+LINK_STORAGE_BYTES = {"f64": 96, "f32": 48, "f16": 36, "bf16": 36}
 SPINOR_BYTES = {"f64": 192, "f32": 96, "f16": 52, "bf16": 52}
+# contraction (K6) per site and source: the solution and four links
+CONTRACT_BYTES = {"f64": 192 + 4 * 96, "f32": 96 + 4 * 48}
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dslash_f16_traffic.json")
 KERNEL_SOURCES = ["paper_1401_6749_amd/csrc/k_dslash.hip", "paper_1401_6749_amd/csrc/tm_dev.h",
@@ -98,6 +108,7 @@ def measure_roofline(torch, tm, inputs, ctx, g, W, workload):
                                                         fout, pitch), n_calls)
     t_launch = t_call / 2  # one launch per output parity
     alg_bytes = vh * (8 * LINK_BYTES[prec] + nrhs * 2 * SPINOR_BYTES[prec])
+    storage_bytes = vh * (8 * LINK_STORAGE_BYTES[prec] + nrhs * 2 * SPINOR_BYTES[prec])
     achieved = alg_bytes / t_launch / 1e9
     # copy ceiling with the library's streaming copy kernel (1 GiB)
     nb = 1 << 30
@@ -118,8 +129,13 @@ def measure_roofline(torch, tm, inputs, ctx, g, W, workload):
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
         "kernel": f"k_dslash_walk {prec} hop, {nrhs} RHS per launch, {dims[0]}^3x{dims[3]}",
-        "alg_bytes_per_launch": alg_bytes, "launch_us": round(t_launch * 1e6, 2),
-        "copy_ceiling_GBs": round(copy_gbs, 1), "kernel_hash": khash,
+        "alg_bytes_per_launch": alg_bytes,
+        "alg_bytes_per_site": 8 * LINK_BYTES[prec] + nrhs * 2 * SPINOR_BYTES[prec],
+        "storage_bytes_per_launch": storage_bytes,
+        "storage_GBs": round(storage_bytes / t_launch / 1e9, 1),
+        "launch_us": round(t_launch * 1e6, 2),
+        "copy_ceiling_GBs": round(copy_gbs, 1), "frac_of_copy_ceiling": round(achieved / copy_gbs, 4),
+        "kernel_hash": khash,
     }
 
 
@@ -141,10 +157,143 @@ def kernel_rates(torch, tm, inputs, ctx, g, W):
         t = event_time(torch, lambda: tm.tm_dslash_ex(ctx, g, "hop", W["kappa"], W["a"], prec, nrhs, fin, pitch,
                                                        fout, pitch), 10) / 2
         alg = vh * (8 * LINK_BYTES[prec] + nrhs * 2 * SPINOR_BYTES[prec])
+        sto = vh * (8 * LINK_STORAGE_BYTES[prec] + nrhs * 2 * SPINOR_BYTES[prec])
         out.append({"prec": prec, "nrhs": nrhs, "launch_us": round(t * 1e6, 1), "alg_GBs": round(alg / t / 1e9, 1),
-                    "frac_8TBs": round(alg / t / 1e9 / HBM_PEAK_GBS, 4)})
+                    "frac_8TBs": round(alg / t / 1e9 / HBM_PEAK_GBS, 4), "storage_GBs": round(sto / t / 1e9, 1)})
         del fin, fout
     return out
+
+
+def contract_rates(torch, tm, inputs, ctx, g, W):
+    """The contraction (K6) alone through tm_contract: 12 FP32 solutions at
+    the solver's slot pitch (the LP harvest's launch shape) and one FP64
+    solution (the HP harvest's), timed with HIP events on the stream it runs
+    on; algorithmic bytes = the solution and four links per site and source
+    (the noise is regenerated from its counter, the neighbour reads are the
+    stencil's own data)."""
+    dims = W["dims"]
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    lt = dims[3]
+    psi = tm.canonical_to_torch(inputs.random_spinor(dims, 3)[None])
+    out = []
+    for prec, n in (("f32", W["batch"]), ("f64", 1)):
+        fb = tm.tm_field_bytes(g, prec, True)
+        pitch = slot_pitch(fb)
+        fin = torch.zeros(n * pitch, dtype=torch.uint8, device="cuda")
+        for r in range(n):
+            tm.tm_field_import(ctx, g, prec, 1, psi, fin[r * pitch:r * pitch + fb])
+        raw = torch.zeros(n * 9 * lt * 32, dtype=torch.float64, device="cuda")
+        ids = list(range(n))
+        t = event_time(torch, lambda: tm.tm_contract(ctx, g, prec, n, fin, pitch, W["noise_seed"], ids, raw), 10)
+        alg = V * n * CONTRACT_BYTES[prec]
+        out.append({"prec": prec, "sources": n, "call_us": round(t * 1e6, 1), "us_per_source": round(t * 1e6 / n, 1),
+                    "alg_bytes": alg, "alg_GBs": round(alg / t / 1e9, 1),
+                    "frac_8TBs": round(alg / t / 1e9 / HBM_PEAK_GBS, 4)})
+        del fin, raw
+    return out
+
+
+def plain_segment(tm, np, ctx, g, W, n_src, t_step, tsm_var, batches=(1, 12)):
+    """Plain FP64 CG (Sec. 2, Eq. estiM: no TSM, FP64 to 1e-10) on the same
+    GPU, one and 12 right-hand sides per launch: sources/s of each, and the
+    TSM speed-up at equal statistical error against the faster of the two,
+    per operator class.  The single-source variance sigma_1^2 comes from the
+    n_src plain sources."""
+    import torch
+
+    lt = W["dims"][3]
+    out = {"n_sources": n_src}
+    best = None
+    sig1 = None
+    for b in batches:
+        Pp = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"], 0, n_src, lp=tm.solver_params("f64", tol=1e-10),
+                           batch=b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rp = tm.tm_loops_tsm(ctx, g, Pp, lt)
+        torch.cuda.synchronize()
+        rate = n_src / (time.perf_counter() - t0)
+        out[f"sources_per_s_batch{b}"] = round(rate, 3)
+        if best is None or rate > best:
+            best = rate
+            out["rhs_per_launch"] = b
+        sig1 = (rp["var_re"] + rp["var_im"]) * n_src
+        out["iters_mean"] = rp["stats"]["lp_iters"] / max(1, rp["stats"]["lp_solves"])
+    out["sources_per_s"] = round(best, 3)
+    ok = (sig1 > 0) & (tsm_var > 0)
+    eff = np.where(ok, sig1 / np.where(ok, tsm_var, 1) / t_step, np.nan)  # plain-source equivalents per s
+    ratio = eff / best
+    out["tsm_effective_speedup_local_median"] = float(np.nanmedian(ratio[:16]))
+    out["tsm_effective_speedup_deriv_median"] = float(np.nanmedian(ratio[16:80]))
+    out["tsm_effective_speedup_sym_median"] = float(np.nanmedian(ratio[80:90]))
+    return out
+
+
+def tsm_rate(tm, ctx, g, W, half=None, steps=2):
+    """TSM loop sources/s of the workload (after one untimed step), LP in the
+    given half precision; returns (sources/s, seconds per step, last result)."""
+    import torch
+
+    lt = W["dims"][3]
+    P = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"], W["n_hp"], W["n_lp"],
+                      hp=tm.solver_params("mixed", tol=1e-10, delta=1e-3),
+                      lp=tm.solver_params("lp", tol=1e-2, half=half or W["half"]), batch=W["batch"])
+    tm.tm_loops_tsm(ctx, g, P, lt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = tm.tm_loops_tsm(ctx, g, P, lt)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    return (W["n_hp"] + W["n_lp"]) / t, t, r
+
+
+def config_segment(tm, np, inputs, ctx, name, plain_sources=64):
+    """Another benchmark configuration on its own seeded gauge field:
+    tsm-24c48 (TSM sources/s with FP16 LP, per-operator loop error against
+    the FP64 path, R_HP/LP, plain FP64 and the equal-error speed-up) or
+    plain-16c32 (the plain FP64 method: sources/s)."""
+    W = WORKLOADS[name]
+    dims = W["dims"]
+    t0 = time.perf_counter()
+    g = tm.tm_load_gauge(ctx, dims, inputs.gauge_field(dims, W["gauge_seed"]), -1, ("f32", "f16", "bf16"))
+    out = {"workload": name, "lattice": list(dims), "kappa": W["kappa"], "two_kappa_mu": W["a"]}
+    try:
+        if W["n_hp"] == 0:
+            import torch
+
+            Pp = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"], 0, W["n_lp"],
+                               lp=tm.solver_params("f64", tol=1e-10), batch=W["batch"])
+            tm.tm_loops_tsm(ctx, g, Pp, dims[3])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rp = tm.tm_loops_tsm(ctx, g, Pp, dims[3])
+            torch.cuda.synchronize()
+            out.update(sources=W["n_lp"], rhs_per_launch=W["batch"],
+                       plain_f64_sources_per_s=round(W["n_lp"] / (time.perf_counter() - t1), 2),
+                       iters_mean=rp["stats"]["lp_iters"] / max(1, rp["stats"]["lp_solves"]))
+        else:
+            rate, t_step, r = tsm_rate(tm, ctx, g, W)
+            out.update(n_hp=W["n_hp"], n_lp=W["n_lp"], tsm_sources_per_s=round(rate, 2),
+                       ms_per_step=round(t_step * 1e3, 1))
+            out["plain_f64"] = plain_segment(tm, np, ctx, g, W, plain_sources, t_step, r["var_re"] + r["var_im"])
+            out["precision"] = precision_segment(tm, np, ctx, g, W)
+            out["r_hp_lp"] = r_hp_lp(tm, ctx, g, W)
+    finally:
+        tm.tm_free_gauge(ctx, g)
+    out["seconds"] = round(time.perf_counter() - t0, 1)
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def write_traffic(fetch_db: str, write_db: str, workload: str) -> None:
@@ -517,8 +666,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tsm-batched-32c64", choices=sorted(WORKLOADS))
-    ap.add_argument("--plain-sources", type=int, default=48)
+    ap.add_argument("--workload", default="tsm-batched-32c64",
+                    choices=sorted(k for k, w in WORKLOADS.items() if w["n_hp"] > 0))
+    ap.add_argument("--plain-sources", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=40,
@@ -603,42 +753,29 @@ def main():
     # ---- plain FP64 CG on the same GPU, and efficiency at equal error ----
     plain = None
     if not args.no_plain:
-        Pp = tm.tsm_params(W["kappa"], W["a"], W["noise_seed"], 0, args.plain_sources,
-                           lp=tm.solver_params("f64", tol=1e-10), batch=1)
-        torch.cuda.synchronize()
-        tp0 = time.perf_counter()
-        rp = tm.tm_loops_tsm(ctx, g, Pp, lt)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - tp0
-        plain_rate = args.plain_sources / tp
-        # single-source variance of the plain FP64 loops, per operator and t
-        sig1 = (rp["var_re"] + rp["var_im"]) * args.plain_sources
-        sig_tsm = last["var_re"] + last["var_im"]
-        t_step = wall / args.steps
-        ok = (sig1 > 0) & (sig_tsm > 0)
-        eff = np.where(ok, sig1 / np.where(ok, sig_tsm, 1) / t_step, np.nan)  # plain-source equivalents per s
-        ratio = eff / plain_rate
-        loc, der = ratio[:16].reshape(-1), ratio[16:80].reshape(-1)
-        plain = {
-            "sources_per_s": round(plain_rate, 3),
-            "n_sources": args.plain_sources,
-            "rhs_per_launch": 1,
-            "iters_mean": rp["stats"]["lp_iters"] / max(1, rp["stats"]["lp_solves"]),
-            "tsm_effective_speedup_local_median": float(np.nanmedian(loc)),
-            "tsm_effective_speedup_deriv_median": float(np.nanmedian(der)),
-        }
-        log(f"plain FP64: {plain_rate:.2f} sources/s; TSM equal-error speedup local "
-            f"{plain['tsm_effective_speedup_local_median']:.1f}x deriv {plain['tsm_effective_speedup_deriv_median']:.1f}x")
+        plain = plain_segment(tm, np, ctx, g, W, args.plain_sources, wall / args.steps,
+                              last["var_re"] + last["var_im"])
+        log(f"plain FP64: {plain['sources_per_s']:.2f} sources/s ({plain['rhs_per_launch']} RHS per launch); TSM "
+            f"equal-error speedup local {plain['tsm_effective_speedup_local_median']:.1f}x deriv "
+            f"{plain['tsm_effective_speedup_deriv_median']:.1f}x")
 
     roofline = measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)
-    rates = None
+    rates = crates = None
     if not args.no_extra:
         rates = kernel_rates(torch, tm, inputs, ctx, g, W)
         log("hop rates: " + ", ".join(f"{r['prec']}x{r['nrhs']} {r['launch_us']}us {r['alg_GBs']}GB/s" for r in rates))
+        crates = contract_rates(torch, tm, inputs, ctx, g, W)
+        log("contraction: " + ", ".join(f"{r['prec']}x{r['sources']} {r['call_us']}us {r['alg_GBs']}GB/s"
+                                        for r in crates))
 
-    precision = rhl = serving = oet = hpe = tdil = None
+    precision = rhl = serving = oet = hpe = tdil = bf16 = configs = None
     if not args.no_extra:
         t0 = time.perf_counter()
+        b_rate, b_step, b_last = tsm_rate(tm, ctx, g, W, half="bf16")
+        bf16 = {"sources_per_s": round(b_rate, 2), "ms_per_step": round(b_step * 1e3, 1),
+                "lp_iters_mean": b_last["stats"]["lp_iters"] / max(1, b_last["stats"]["lp_solves"]),
+                "lp": "bf16 storage (per-site FP32 scale), FP32 arithmetic, truncated at 1e-2"}
+        log(f"BF16 LP: {b_rate:.1f} sources/s")
         precision = precision_segment(tm, np, ctx, g, W)
         rhl = r_hp_lp(tm, ctx, g, W)
         oet = oet_segment(tm, np, ctx, g, W)
@@ -652,6 +789,11 @@ def main():
             f"with HPE {tdil['error_ratio_tdil_hpe_local_median']:.2f} at equal solves")
         log(f"precision and R_HP/LP segments in {time.perf_counter() - t0:.1f}s; R_HP/LP {rhl['value']} "
             f"(local only {rhl['local']})")
+        if args.workload == "tsm-batched-32c64":
+            configs = {}
+            for name in ("plain-16c32", "tsm-24c48"):
+                configs[name] = config_segment(tm, np, inputs, ctx, name)
+                log(f"{name}: {configs[name]}")
         if args.serve_requests > 0:
             try:
                 serving = serving_segment(tm, np, inputs, ctx, g, W, value, args.serve_requests, load=args.serve_load)
@@ -680,6 +822,7 @@ def main():
         t_hp_src = t_it * (hp_it + 4.0)
         t_tsm = W["n_hp"] * t_hp_src + n_src * t_lp_src
         cpu = {"value": round(n_src / t_tsm, 6), "unit": "sources/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": f"1 LP source (FP64, tol 1e-2, {it_lp} iterations, contraction) at "
                          f"{dims[0]}^3x{lt}: {t_lp_src:.1f}s; HP sources extrapolated from it with the GPU's "
                          f"mean HP iteration count ({hp_it:.0f})"}
@@ -725,6 +868,9 @@ def main():
         "serving": serving,
         "roofline": roofline,
         "kernel_rates": rates,
+        "contraction_rates": crates,
+        "bf16_lp": bf16,
+        "configs": configs,
         "cpu_baseline": cpu,
     }
     tm.tm_free_gauge(ctx, g)

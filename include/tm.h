@@ -360,6 +360,25 @@ int tm_loops_tdil(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *p
                   const int *phases, int n_phases, int hpe, double *est, double *var_re, double *var_im, double *raw,
                   tm_tsm_stats *stats);
 
+/* The contraction step of tm_loops_tsm alone, for given solutions: loops
+ * at every insertion time (Sec. 2.2, last paragraph) of the local and
+ * one-derivative operators (abstract) as spin matrices
+ *   raw[i][9][Lt][4][4][2], kinds 0 local, 1..4 F^nu, 5..8 B^nu as in
+ *   tm_loops_tsm, of eta_i = eta(noise_seed, src_ids[i]) (as tm_z4_source)
+ *   and the solution s_i (any field; normally s_i = M^-1 eta_i).
+ *   prec     TM_PREC_F64 or TM_PREC_F32: s and the links in that precision;
+ *            FP32 products are summed in FP64
+ *   s        device, n full-lattice fields in the layout of prec (see
+ *            tm_field_bytes), field i at s + i * s_stride; s_stride a
+ *            multiple of 256 and at least one field
+ *   src_ids  host, n source ids;  raw  device, n * 9 * Lt * 32 doubles
+ *   n        1..16
+ * Asynchronous on hip_stream.  Its scratch (Z4 codes, partial sums) is the
+ * context's, grown on demand (with a device synchronisation).  Errors:
+ * TM_ERR_ARG, TM_ERR_NOMEM, TM_ERR_HIP. */
+int tm_contract(tm_context *ctx, const tm_gauge *gauge, tm_prec prec, int n, const void *s, size_t s_stride,
+                uint64_t noise_seed, const uint64_t *src_ids, double *raw, void *hip_stream);
+
 /* Project spin matrices [n][9][Lt][4][4][2] (host) onto the 90 operator
  * loops [n][TM_N_OPS][Lt][2] (host), as in tm_loops_tsm. */
 int tm_project_loops(int n, int lt, const double *raw, double *ops);

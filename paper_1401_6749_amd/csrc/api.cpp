@@ -667,6 +667,49 @@ extern "C" int tm_z4_source(tm_context *ctx, const int dims[4], uint64_t seed, u
 }
 
 // ---------------------------------------------------------------------------
+// contractions of given solutions with their Z4 sources
+// ---------------------------------------------------------------------------
+extern "C" int tm_contract(tm_context *ctx, const tm_gauge *G, tm_prec prec, int n, const void *s, size_t s_stride,
+                           uint64_t noise_seed, const uint64_t *src_ids, double *raw, void *hip_stream)
+{
+    if (!ctx) return TM_ERR_ARG;
+    const int p = prec_index(prec);
+    if (!G || (p != P64 && p != P32)) return set_err(ctx, TM_ERR_ARG, "tm_contract: gauge, or precision not F64/F32");
+    if (!(G->precs & (1u << p))) return set_err(ctx, TM_ERR_ARG, "tm_contract: gauge not loaded in this precision");
+    if (n < 1 || n > MAX_SLOTS || !s || !src_ids || !raw)
+        return set_err(ctx, TM_ERR_ARG, "tm_contract: n must be 1..%d and every pointer set", MAX_SLOTS);
+    const Geom &g = G->g;
+    const size_t hb = half_bytes(p, g);
+    if (s_stride < 2 * hb || s_stride % 256)
+        return set_err(ctx, TM_ERR_ARG, "tm_contract: s_stride must be a multiple of 256 and at least one field");
+    const size_t codes_b = ((size_t)n * 2 * g.vh * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t need = codes_b + (size_t)n * contract_part_doubles(g) * sizeof(double);
+    if (ctx->ct_tmp_bytes < need) {
+        (void)hipDeviceSynchronize();
+        dfree(ctx, ctx->ct_tmp);
+        ctx->ct_tmp = dalloc(ctx, need);
+        ctx->ct_tmp_bytes = ctx->ct_tmp ? need : 0;
+        if (!ctx->ct_tmp) return set_err(ctx, TM_ERR_NOMEM, "tm_contract: no memory for its scratch");
+    }
+    uint32_t *codes = (uint32_t *)ctx->ct_tmp;
+    double *cpart = (double *)((char *)ctx->ct_tmp + codes_b);
+    hipStream_t st = (hipStream_t)hip_stream;
+    Z4Sources Z{};
+    RawOuts R{};
+    const size_t per = (size_t)9 * g.L[3] * 32;
+    for (int i = 0; i < n; i++) {
+        Z.seed[i] = noise_seed;
+        Z.src[i] = src_ids[i];
+        R.p[i] = raw + i * per;
+    }
+    launch_z4_codes(g, Z, n, codes, st);
+    const char *se = (const char *)s;
+    launch_contract(p, g, G->links[p], se, se + hb, s_stride, codes, cpart, R, n, st);
+    TM_HIP(ctx, hipGetLastError());
+    return TM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // projection on the host (utility for raw spin matrices)
 // ---------------------------------------------------------------------------
 extern "C" int tm_project_loops(int n, int lt, const double *raw, double *ops)

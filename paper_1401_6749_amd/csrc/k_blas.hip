@@ -4,6 +4,8 @@
 #include "tm_dev.h"
 #include "tm_launch.h"
 
+#include <algorithm>
+
 namespace tmk {
 
 // Fixed-order sum of n doubles by one block of BLOCK threads: thread i sums
@@ -377,24 +379,40 @@ void launch_site_diag(const Geom &g, int mode, double a, const char *in, char *o
 }
 
 // ---------------------------------------------------------------------------
-// Streaming copy (16-byte vectors, grid-stride): the measured HBM ceiling.
+// Streaming copy, the measured HBM ceiling: each block moves CU_VEC * BLOCK
+// consecutive 16-byte vectors, every thread issuing its CU_VEC loads before
+// any store (several loads in flight per lane), streamed past the caches.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(BLOCK) void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+constexpr int CU_VEC = 4;
+
+__global__ __launch_bounds__(BLOCK) void k_stream_copy(const tm_u32x4 *__restrict__ src, tm_u32x4 *__restrict__ dst,
                                                        size_t n)
 {
-    size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * BLOCK;
-    for (; i < n; i += stride) dst[i] = src[i];
+    const size_t base = (size_t)blockIdx.x * BLOCK * CU_VEC + threadIdx.x;
+    tm_u32x4 v[CU_VEC];
+#pragma unroll
+    for (int u = 0; u < CU_VEC; u++) {
+        const size_t i = base + (size_t)u * BLOCK;
+        if (i < n) v[u] = __builtin_nontemporal_load(&src[i]);
+    }
+#pragma unroll
+    for (int u = 0; u < CU_VEC; u++) {
+        const size_t i = base + (size_t)u * BLOCK;
+        if (i < n) __builtin_nontemporal_store(v[u], &dst[i]);
+    }
 }
 
 void launch_stream_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
 {
     const size_t n = bytes / 16;
-    size_t blocks = (n + BLOCK - 1) / BLOCK;
-    if (blocks > 256 * 64) blocks = 256 * 64;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(BLOCK), 0, s, (const uint4 *)src, (uint4 *)dst,
-                       n);
+    if (n == 0) return;
+    const size_t blocks = (n + (size_t)BLOCK * CU_VEC - 1) / ((size_t)BLOCK * CU_VEC);
+    for (size_t b0 = 0; b0 < blocks; b0 += 0x7FFFFFFF) {
+        const size_t nb = std::min<size_t>(blocks - b0, 0x7FFFFFFF);
+        const size_t off = b0 * BLOCK * CU_VEC;
+        hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)nb), dim3(BLOCK), 0, s, (const tm_u32x4 *)src + off,
+                           (tm_u32x4 *)dst + off, n - off);
+    }
 }
 
 }  // namespace tmk

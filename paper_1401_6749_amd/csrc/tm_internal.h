@@ -34,6 +34,9 @@ struct tm_context {
     // scratch of tm_dslash (grown on demand)
     void *op_tmp = nullptr;
     size_t op_tmp_bytes = 0;
+    // scratch of tm_contract: Z4 codes and partial sums (grown on demand)
+    void *ct_tmp = nullptr;
+    size_t ct_tmp_bytes = 0;
 };
 
 struct tm_gauge {

@@ -131,6 +131,8 @@ _sig = {
     "tm_loops_tdil": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_int, c_void_p, c_int, c_int,
                               c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(tm_tsm_stats)]),
     "tm_project_loops": (c_int, [c_int, c_int, c_void_p, c_void_p]),
+    "tm_contract": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_size_t, c_uint64, c_void_p, c_void_p,
+                            c_void_p]),
     "tm_serve_status_get": (c_int, [c_void_p, ctypes.POINTER(tm_serve_status)]),
     "tm_serve_create": (c_int, [c_void_p, c_int, c_size_t, ctypes.POINTER(c_void_p)]),
     "tm_serve_submit": (c_int, [c_void_p, ctypes.POINTER(tm_request)]),
@@ -393,6 +395,15 @@ def tm_loops_tdil(ctx, gauge, params, lt, spacing, phases=None, hpe=False, want_
     extra = (int(spacing), None if ph is None else ph.ctypes.data, 0 if ph is None else int(ph.size), int(bool(hpe)))
     names = ("std", "hpe") if hpe else ("std",)
     return _loops2("tm_loops_tdil", names, ctx, gauge, params, lt, want_raw, check, extra)
+
+
+def tm_contract(ctx, gauge, prec, n, s, s_stride, noise_seed, src_ids, raw, stream=None):
+    """Spin matrices of n solutions s (device, layout of prec) with their Z4
+    sources into raw (device, n * 9 * lt * 32 doubles)."""
+    ids = np.ascontiguousarray(np.asarray(src_ids, dtype=np.uint64))
+    assert ids.size == n
+    _check(ctx, _lib.tm_contract(ctx, gauge, PREC[prec], int(n), _ptr(s), int(s_stride), c_uint64(int(noise_seed)),
+                                 ids.ctypes.data, _ptr(raw), _stream(stream)), "tm_contract")
 
 
 def tm_project_loops(raw: np.ndarray) -> np.ndarray:

@@ -166,3 +166,33 @@ def test_fullsize_loops_tdil_one_timeslice(oracle, big):
         assert GU.relerr(r["raw_std_lp"][j][0], ref["raw"]["lp_std"][j][0]) < 5e-3, j
     est = r["est_std"]
     assert np.isfinite(est[:16, 8]).all() and np.isnan(est[:16, 7]).all() and np.isnan(est[:16, 9]).all()
+
+
+def test_fullsize_contract_12(oracle, big):
+    """tm_contract at 32^3x64 with 12 FP32 solutions at the solver's slot
+    pitch (the LP harvest's contraction shape the bench times) and one FP64
+    solution: sampled sources against the oracle's contraction."""
+    torch = GU.torch_mod()
+    from paper_1401_6749_amd import tm
+
+    U, g = big
+    ctx = GU.context()
+    lt = DIMS[3]
+    psis = [inputs.random_spinor(DIMS, 31), inputs.random_spinor(DIMS, 32)]
+    dev = [GU.to_dev(p[None]) for p in psis]
+    ids = list(range(100, 112))
+    for prec, n, tol in (("f32", 12, 2e-6), ("f64", 1, 1e-13)):
+        fb = tm.tm_field_bytes(g, prec, True)
+        pitch = slot_pitch(fb)
+        fin = torch.zeros(n * pitch, dtype=torch.uint8, device="cuda")
+        for r in range(n):
+            tm.tm_field_import(ctx, g, prec, 1, dev[r % 2], fin[r * pitch:r * pitch + fb])
+        raw = torch.zeros(n * 9 * lt * 32, dtype=torch.float64, device="cuda")
+        tm.tm_contract(ctx, g, prec, n, fin, pitch, 104, ids[:n], raw)
+        torch.cuda.synchronize()
+        got = raw.cpu().numpy().reshape(n, 9, lt, 4, 4, 2)
+        del fin, raw
+        for r in sorted({0, n - 1}):
+            want = oracle.contract(DIMS, -1, U, oracle.z4_source(DIMS, 104, ids[r]), psis[r % 2])
+            gr = got[r][..., 0] + 1j * got[r][..., 1]
+            assert GU.relerr(gr, want) < tol, (prec, r, GU.relerr(gr, want))

@@ -579,3 +579,40 @@ def test_loops_local_only_matches_full_run():
         assert rc == tm.TM_ERR_ARG
     finally:
         tm.tm_serve_destroy(srv)
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-6)])
+@pytest.mark.parametrize("tbc", [-1, 1])
+def test_contract_parity(oracle, prec, tol, tbc):
+    """tm_contract, the contraction step alone (Sec. 2.2: loops at every
+    insertion time, local and one-derivative kinds), on random fields at a
+    padded stride against the oracle's contraction of the same Z4 sources and
+    fields: all nine kinds of spin matrices, both time boundary conditions,
+    a lattice whose timeslices are not whole contraction chunks."""
+    torch = GU.torch_mod()
+    from paper_1401_6749_amd import tm
+
+    ctx = GU.context()
+    dims = (6, 4, 2, 8)
+    V = int(np.prod(dims))
+    U = inputs.gauge_field(dims, seed=23)
+    g = GU.load(dims, U, tbc)
+    n, seed, ids = 3, 77, [0, 5, 1023]
+    psi = np.stack([inputs.random_spinor(dims, 50 + i) for i in range(n)])
+    fb = tm.tm_field_bytes(g, prec, True)
+    stride = (fb + 255) // 256 * 256 + 256
+    fin = torch.zeros(n * stride, dtype=torch.uint8, device="cuda")
+    for i in range(n):
+        tm.tm_field_import(ctx, g, prec, 1, GU.to_dev(psi[i][None]), fin[i * stride:i * stride + fb])
+    lt = dims[3]
+    raw = torch.zeros(n * 9 * lt * 32, dtype=torch.float64, device="cuda")
+    tm.tm_contract(ctx, g, prec, n, fin, stride, seed, ids, raw)
+    torch.cuda.synchronize()
+    got = raw.cpu().numpy().reshape(n, 9, lt, 4, 4, 2)
+    got = got[..., 0] + 1j * got[..., 1]
+    for i in range(n):
+        want = oracle.contract(dims, tbc, U, oracle.z4_source(dims, seed, ids[i]), psi[i])
+        assert GU.relerr(got[i], want) < tol, (prec, i, GU.relerr(got[i], want))
+        for k in range(9):
+            assert GU.relerr(got[i][k], want[k]) < 10 * tol, (prec, i, k)
+    assert V == 384
