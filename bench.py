@@ -593,8 +593,11 @@ def serving_segment(tm, np, inputs, ctx, g_big, W, rate_big, n_req, budget_gb=32
     srv = tm.tm_serve_create(ctx, slots=W["batch"], workspace_budget=int(budget_gb) << 30)
     res = {}
     stalled = False
-    # a request still missing this long after the last arrival is reported, not waited for
-    deadline = float(arrivals[-1]) + 20.0 * sum(r[4] for r in reqs) + 60.0
+    # a request still missing this long after the last arrival is reported, not
+    # waited for; so is a server that has changed nothing for STALL_S seconds
+    # while work is outstanding
+    deadline = float(arrivals[-1]) + 2.0 * sum(r[4] for r in reqs) + 30.0
+    STALL_S = 30.0
     try:
         t0 = time.perf_counter()
         k = 0
@@ -612,8 +615,12 @@ def serving_segment(tm, np, inputs, ctx, g_big, W, rate_big, n_req, budget_gb=32
                 st = tm.tm_serve_status_get(srv)
                 log(f"serving: {len(res)}/{n_req} done, {k} submitted at {now:.0f}s; queued {st['queued']}, "
                     f"active {st['active']}, batches {st['batches']}, pending jobs {st['pending_jobs']}, "
-                    f"slots {st['running_slots']}, arena {st['arena_used'] >> 20}/{st['arena_size'] >> 20} MiB")
+                    f"slots {st['running_slots']}, arena {st['arena_used'] >> 20}/{st['arena_size'] >> 20} MiB, "
+                    f"no progress for {st['stall_s']:.1f}s")
                 next_log += 10.0
+                if st["stall_s"] > STALL_S:
+                    stalled = True
+                    raise RuntimeError(f"serving: the server made no progress for {st['stall_s']:.0f}s: {st}")
             if now > deadline:
                 stalled = True
                 missing = sorted(set(range(k)) - set(res))
@@ -671,7 +678,7 @@ def main():
     ap.add_argument("--plain-sources", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=40,
+    ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests in the serving segment (0 skips it)")
     ap.add_argument("--serving-only", action="store_true", help="only the serving segment (after one warm-up step)")
     ap.add_argument("--serve-load", type=float, default=0.8,
@@ -769,6 +776,7 @@ def main():
                                         for r in crates))
 
     precision = rhl = serving = oet = hpe = tdil = bf16 = configs = None
+    stalled_server = False
     if not args.no_extra:
         t0 = time.perf_counter()
         b_rate, b_step, b_last = tsm_rate(tm, ctx, g, W, half="bf16")
@@ -800,13 +808,16 @@ def main():
             except RuntimeError as e:
                 serving = {"error": str(e)}
                 log(f"serving failed: {e}")
+                # a stalled server still holds the device: the line is printed
+                # without the CPU baseline and the process leaves without teardown
+                stalled_server = "no progress" in str(e) or "not done" in str(e)
             else:
                 log(f"serving: {serving['requests']} requests, p50 {serving['latency_p50_s']}s, "
                     f"p99 {serving['latency_p99_s']}s, {serving['sources_per_s']} sources/s")
 
     # ---- CPU oracle on a bounded sample (one LP source at the same lattice) ----
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not stalled_server:
         from oracle import oracle as O
 
         O.lib()
@@ -873,6 +884,11 @@ def main():
         "configs": configs,
         "cpu_baseline": cpu,
     }
+    if stalled_server:
+        print(json.dumps(line), flush=True)
+        sys.stdout.flush()
+        sys.stderr.flush()
+        os._exit(0)
     tm.tm_free_gauge(ctx, g)
     tm.tm_destroy(ctx)
     print(json.dumps(line), flush=True)

@@ -438,6 +438,8 @@ typedef struct tm_serve_status {
     int worker_error;         /* first error met by the worker (TM_OK if none) */
     size_t arena_used, arena_size, arena_largest_free;
     double t_snapshot;        /* server clock of the snapshot */
+    double stall_s;           /* seconds since the worker last changed a request or batch
+                                 while work was outstanding (0 when idle) */
 } tm_serve_status;
 /* Copy the latest snapshot into *out.  Errors: TM_ERR_ARG. */
 int tm_serve_status_get(tm_server *srv, tm_serve_status *out);

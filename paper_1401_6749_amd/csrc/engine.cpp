@@ -20,12 +20,7 @@ using namespace tmk;
 
 namespace tmi {
 
-Kind kind_of(const tm_solver_params &p)
-{
-    if (p.mode == TM_SOLVE_MIXED) return K_MIXED;
-    if (p.mode == TM_SOLVE_LP) return p.half_prec == TM_PREC_BF16 ? K_LPBF : K_LP16;
-    return K_F64;
-}
+Kind kind_of(const tm_solver_params &p) { return kind_of_mode(p.mode, p.half_prec); }
 
 int kind_prec(Kind k)
 {
