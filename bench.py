@@ -687,6 +687,8 @@ def main():
                     help="skip the hop-rate, precision, R_HP/LP, estimator-variant and serving segments")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the copy calibration and the roofline kernel (for counter runs)")
+    ap.add_argument("--contract-only", action="store_true",
+                    help="only the contraction rates (tm_contract; for kernel traces and counter runs)")
     ap.add_argument("--scan", metavar="OUT_JSON",
                     help="run the TSM tuning scan (after one warm-up step), write it to OUT_JSON and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -716,8 +718,12 @@ def main():
     U = inputs.gauge_field(dims, W["gauge_seed"])
     g = tm.tm_load_gauge(ctx, dims, U, -1, ("f32", "f16", "bf16"))
     log(f"gauge {dims} ready in {time.time() - t0:.1f}s")
-    if args.roofline_only:
-        print(json.dumps({"roofline": measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)}), flush=True)
+    if args.roofline_only or args.contract_only:
+        if args.roofline_only:
+            out = {"roofline": measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)}
+        else:
+            out = {"contraction_rates": contract_rates(torch, tm, inputs, ctx, g, W)}
+        print(json.dumps(out), flush=True)
         tm.tm_free_gauge(ctx, g)
         tm.tm_destroy(ctx)
         return
