@@ -516,14 +516,13 @@ static void enqueue_iteration(Batch *b)
     A.out = nullptr;
     A.out_par = 0;
     A.coef = CM_MHAT_DAG;
-    A.x = b->x;
     A.r = b->r;
-    A.p = b->p;
     A.xr_slot = b->hxr;
-    A.p_slot = b->hsp;
     launch_dslash(sp, true, EPI_CGUPD, true, A, b->stream);
     launch_cg_beta(b->st, b->partial, b->S, b->nblk, b->stream);
-    launch_p_update(sp, b->xr, b->G->g, b->p, b->hsp, b->r, b->hxr, b->st, b->S, b->ctx->swz, b->stream);
+    // x += alpha p (for every slot that stepped) and p = r + beta p
+    launch_p_update(sp, b->xr, b->G->g, b->p, b->hsp, b->r, b->hxr, b->x, b->hxr, b->st, b->S, b->ctx->swz,
+                    b->stream);
 }
 
 int batch_launch_chunk(Batch *b)
@@ -589,7 +588,8 @@ static void reliable_update_run(Batch *b, int s0, int n)
             b->b64 + s0 * b->h64, b->h64);
     launch_convert(P64, b->xr, g, Ce, w, r32, b->hxr, n, s);
     launch_reliable_finish(b->st + s0, part, b->nblk, n, s);
-    launch_p_update(b->sp, b->xr, g, b->p + s0 * b->hsp, b->hsp, r32, b->hxr, b->st + s0, n, b->ctx->swz, s);
+    launch_p_update(b->sp, b->xr, g, b->p + s0 * b->hsp, b->hsp, r32, b->hxr, nullptr, 0, b->st + s0, n, b->ctx->swz,
+                    s);
     for (int i = 0; i < n; i++) b->slot_updates[s0 + i]++;
 }
 

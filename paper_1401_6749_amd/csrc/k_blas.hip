@@ -24,15 +24,20 @@ __global__ __launch_bounds__(BLOCK) void k_cg_alpha(SlotState *st, const double 
     __shared__ double lds[BLOCK / 64];
     const int slot = blockIdx.x;
     SlotState &S = st[slot];
-    if (S.status != ST_RUNNING) return;
+    if (S.status != ST_RUNNING) {
+        if (threadIdx.x == 0) S.xpend = 0;  // no step this iteration
+        return;
+    }
     const double pap = sum_fixed(partial + (size_t)slot * nblk, nblk, lds);
     if (threadIdx.x == 0) {
         S.pap = pap;
         if (!finite_pos(pap)) {
             S.status = ST_NUMERIC;
             S.alpha = 0.0;
+            S.xpend = 0;
         } else {
             S.alpha = S.rr / pap;
+            S.xpend = 1;
         }
     }
 }
@@ -86,6 +91,7 @@ __global__ void k_slot_start(SlotState *st, const double *partial, int nblk, Slo
         S.rr_new = rr0;
         S.rr_ref = rr0;
         S.alpha = S.beta = S.pap = 0.0;
+        S.xpend = 0;
         if (!(rr0 >= 0.0 && rr0 < 1.0e300))
             S.status = ST_NUMERIC;
         else if (rr0 == 0.0)
@@ -169,29 +175,47 @@ void launch_reduce(const double *partial, int nblk, int n, double *out, hipStrea
 // ---------------------------------------------------------------------------
 // p = r + beta p
 // ---------------------------------------------------------------------------
+// End of a CG iteration per slot: x += alpha p if the iteration took a step
+// (x != nullptr and the slot's step is owed), then p = r + beta p if the slot
+// keeps running.  Both read the old p.
 template <int SP, int XR>
 __global__ __launch_bounds__(BLOCK) void k_p_update(Geom g, char *p, size_t p_slot, const char *r, size_t r_slot,
-                                                    SlotState *st, int nslot, int nblk, int swz)
+                                                    char *x, size_t x_slot, SlotState *st, int nslot, int nblk,
+                                                    int swz)
 {
     using T = typename Real<SP>::T;
     int sblk, slot;
     if (!map_block(nblk, nslot, swz, sblk, slot)) return;
     const SlotState &S = st[slot];
-    if (S.status != ST_RUNNING) return;
+    const bool step = x != nullptr && S.xpend != 0;
+    const bool run = S.status == ST_RUNNING;
+    if (!step && !run) return;
     const int cb = sblk * BLOCK + threadIdx.x;
     if (cb >= g.vh) return;
-    const T beta = (T)S.beta;
-    cpx<T> pv[12], rv[12];
+    cpx<T> pv[12];
     char *ps = p + (size_t)slot * p_slot;
     SpinorIO<SP>::load(ps, g.vh, cb, pv);
-    SpinorIO<XR>::load(r + (size_t)slot * r_slot, g.vh, cb, rv);
+    if (step) {
+        cpx<T> xv[12];
+        char *xs = x + (size_t)slot * x_slot;
+        SpinorIO<XR>::load(xs, g.vh, cb, xv);
+        const T al = (T)S.alpha;
 #pragma unroll
-    for (int k = 0; k < 12; k++) pv[k] = rv[k] + cscale(beta, pv[k]);
-    SpinorIO<SP>::store(ps, g.vh, cb, pv);
+        for (int k = 0; k < 12; k++) xv[k] = xv[k] + cscale(al, pv[k]);
+        SpinorIO<XR>::store(xs, g.vh, cb, xv);
+    }
+    if (run) {
+        cpx<T> rv[12];
+        const T beta = (T)S.beta;
+        SpinorIO<XR>::load(r + (size_t)slot * r_slot, g.vh, cb, rv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) pv[k] = rv[k] + cscale(beta, pv[k]);
+        SpinorIO<SP>::store(ps, g.vh, cb, pv);
+    }
 }
 
-void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot,
-                     SlotState *st, int nslot, int swz, hipStream_t s)
+void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot, char *x,
+                     size_t x_slot, SlotState *st, int nslot, int swz, hipStream_t s)
 {
     const int nblk = nblk_of(g);
     const int total = nblk * nslot;
@@ -199,7 +223,7 @@ void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, cons
 #define TMK_P(SP, XR)                                                                                   \
     if (sp == SP && xr == XR) {                                                                        \
         hipLaunchKernelGGL((k_p_update<SP, XR>), dim3(grid), dim3(BLOCK), 0, s, g, p, p_slot, r, r_slot, \
-                           st, nslot, nblk, swz);                                                       \
+                           x, x_slot, st, nslot, nblk, swz);                                            \
         return;                                                                                         \
     }
     TMK_P(P64, P64)

@@ -500,20 +500,17 @@ __device__ __forceinline__ double epilogue(const DslashArgs &A, int slot, int cb
             for (int k = 0; k < 12; k++) part += (double)norm2(v[k]);
         }
     } else if (EPI == EPI_CGUPD) {
-        cpx<T> p[12], x[12], rr[12];
-        SpinorIO<SP>::load(A.p + (size_t)slot * A.p_slot, vh, cb, p);
-        char *xs = A.x + (size_t)slot * A.xr_slot;
+        // r -= alpha Ap; x += alpha p waits for the direction update, which
+        // reads p anyway, so this kernel touches two fields fewer
+        cpx<T> rr[12];
         char *rs = A.r + (size_t)slot * A.xr_slot;
-        SpinorIO<XR>::load(xs, vh, cb, x);
         SpinorIO<XR>::load(rs, vh, cb, rr);
         const T al = (T)alpha;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            x[k] = x[k] + cscale(al, p[k]);
             rr[k] = rr[k] - cscale(al, v[k]);
             part += (double)norm2(rr[k]);
         }
-        SpinorIO<XR>::store(xs, vh, cb, x);
         SpinorIO<XR>::store(rs, vh, cb, rr);
     } else if (EPI == EPI_START) {
         // start of a CG solve: r = p = v and x = 0 in the CG storage

@@ -24,9 +24,11 @@ int launch_dslash_codes(int sp, int src, const DslashArgs &A, hipStream_t s);
 // ---- CG scalars (one block per slot, fixed summation order) ----
 void launch_cg_alpha(SlotState *st, const double *partial, int nslot, int nblk, hipStream_t s);
 void launch_cg_beta(SlotState *st, const double *partial, int nslot, int nblk, hipStream_t s);
-// p = r + beta p for running slots (sp = p precision, xr = r precision)
-void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot,
-                     SlotState *st, int nslot, int swz, hipStream_t s);
+// end of a CG iteration: x += alpha p for slots whose iteration took a step
+// (skipped when x is null: after reliable updates), then p = r + beta p for
+// running slots (sp = p precision, xr = x and r precision)
+void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot, char *x,
+                     size_t x_slot, SlotState *st, int nslot, int swz, hipStream_t s);
 // start n consecutive slots: rr0 = sum of the slot's nblk partials, status
 // RUNNING (or CONVERGED if rr0 == 0); parameters per slot
 struct SlotStartParams {

@@ -82,6 +82,8 @@ struct alignas(128) SlotState {
     double rr_ref;    // |r|^2 at the last reliable update
     double alpha, beta, pap;
     double rr_new;    // last |r|^2 (sloppy) computed by the beta kernel
+    int xpend;        // 1: this iteration's x += alpha p is owed (set by the alpha kernel,
+                      // applied by the direction update at the end of the iteration)
 };
 
 // Site-local coefficient sets of the Dslash epilogue out = P*in2 + Q*hop(in),
@@ -103,7 +105,7 @@ enum : int {
 enum : int {
     EPI_PLAIN = 0,  // out = P in2 + Q hop
     EPI_NORM = 1,   // as PLAIN, plus per-block |out|^2
-    EPI_CGUPD = 2,  // Ap = P in2 + Q hop; x += alpha p; r -= alpha Ap; per-block |r|^2
+    EPI_CGUPD = 2,  // Ap = P in2 + Q hop; r -= alpha Ap; per-block |r|^2 (x += alpha p in the direction update)
     EPI_RESID = 3,  // out = b - (P in2 + Q hop); per-block |out|^2
     EPI_START = 4   // v = P in2 + Q hop; r = out = v and x = 0 in the CG storage precision; per-block |v|^2
 };
@@ -130,7 +132,7 @@ struct DslashArgs {
     int gouter;                    // slot groups slowest in the block order (set by the launcher)
     int wcy, wcz;                  // timeslice-walk chunk: y rows x z planes of full x rows (set by the launcher)
     double *partial;            // [nslot][ntile]
-    // EPI_CGUPD
+    // EPI_CGUPD (r), EPI_START (x, r)
     char *x, *r;
     const char *p;
     size_t xr_slot, p_slot;
