@@ -338,6 +338,42 @@ def write_traffic(fetch_db: str, write_db: str, workload: str) -> None:
     print(json.dumps(out))
 
 
+def trace_summary(trace_dir: str, command: str, top: int = 40) -> str:
+    """Text summary of a rocprofv3 --kernel-trace --stats --output-format csv
+    run: per kernel calls, total / average / min / max duration, share of the
+    total kernel time, and the launch resources from the trace."""
+    import csv
+    import glob
+
+    stats = glob.glob(os.path.join(trace_dir, "*_kernel_stats.csv"))
+    trace = glob.glob(os.path.join(trace_dir, "*_kernel_trace.csv"))
+    if not stats or not trace:
+        raise SystemExit(f"{trace_dir}: no rocprofv3 kernel stats / trace csv")
+    res = {}
+    with open(trace[0]) as f:
+        for row in csv.DictReader(f):
+            res.setdefault(row["Kernel_Name"], (row["VGPR_Count"], row["Accum_VGPR_Count"], row["Scratch_Size"],
+                                                int(row["Grid_Size_X"]) * int(row["Grid_Size_Y"]),
+                                                row["Workgroup_Size_X"]))
+    rows = []
+    with open(stats[0]) as f:
+        for row in csv.DictReader(f):
+            rows.append(row)
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = ["# rocprofv3 kernel trace summary", f"# command: {command}",
+           "# durations in microseconds; share of total kernel time; vgpr/agpr/scratch (bytes per lane), grid, block",
+           f"{'kernel':80s} {'calls':>6s} {'total_us':>12s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} "
+           f"{'share':>6s} vgpr agpr scratch grid block"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+        name = r["Name"]
+        v = res.get(name, ("?", "?", "?", "?", "?"))
+        out.append(f"{name[:80]:80s} {int(r['Calls']):6d} {float(r['TotalDurationNs']) / 1e3:12.1f} "
+                   f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                   f"{100 * float(r['TotalDurationNs']) / total:5.1f}% {v[0]} {v[1]} {v[2]} {v[3]} {v[4]}")
+    out.append(f"# {len(rows)} kernels, {sum(int(r['Calls']) for r in rows)} dispatches, {total / 1e6:.1f} ms of kernel time")
+    return "\n".join(out) + "\n"
+
+
 def op_errors(tm, np, test, ref):
     """Per-operator relative error ||L_test - L_ref|| / ||L_ref|| over (t, source)
     of raw spin matrices (n, 9, T, 4, 4), summarised per operator class."""
@@ -691,10 +727,19 @@ def main():
                     help="only the contraction rates (tm_contract; for kernel traces and counter runs)")
     ap.add_argument("--scan", metavar="OUT_JSON",
                     help="run the TSM tuning scan (after one warm-up step), write it to OUT_JSON and exit")
+    ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_DIR", "OUT_TXT", "COMMAND"),
+                    help="write a text summary of a rocprofv3 --kernel-trace --stats --output-format csv run "
+                         "(the command that produced it as the third argument) and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the roofline kernel's HBM traffic from two rocprofv3 --pmc databases "
                          "(FETCH_SIZE, WRITE_SIZE) of --roofline-only runs and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        txt = trace_summary(args.trace_summary[0], args.trace_summary[2])
+        with open(args.trace_summary[1], "w") as f:
+            f.write(txt)
+        print(txt, end="")
+        return
     if args.traffic_from:
         write_traffic(args.traffic_from[0], args.traffic_from[1], args.workload)
         return
