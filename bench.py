@@ -664,6 +664,7 @@ def serving_segment(tm, np, inputs, ctx, g_big, W, rate_big, n_req, budget_gb=32
                                    f"server {tm.tm_serve_status_get(srv)}; last error: {tm.tm_last_error(ctx)}")
             time.sleep(0.0005)
         wall = time.perf_counter() - t0
+        st_end = tm.tm_serve_status_get(srv)
         # one request again alone: its result must have the same bits
         probe = min(range(n_req), key=lambda i: reqs[i][4])
         tm.tm_serve_submit(srv, reqs[probe][1], reqs[probe][2], 10 ** 6)
@@ -701,6 +702,10 @@ def serving_segment(tm, np, inputs, ctx, g_big, W, rate_big, n_req, budget_gb=32
         "queue_wait_p50_s": round(float(np.percentile(wait, 50)), 3),
         "sources_per_s": round(n_src / wall, 1), "wall_s": round(wall, 2),
         "alone_equals_mix": same,
+        # device utilisation over the mix: share of the time with a chunk on the
+        # GPU, and occupied solver slots averaged over time
+        "device_busy_frac": round(min(1.0, st_end["busy_s"] / wall), 3),
+        "mean_occupied_slots": round(st_end["slot_s"] / wall, 2),
     }
 
 

@@ -440,6 +440,8 @@ typedef struct tm_serve_status {
     double t_snapshot;        /* server clock of the snapshot */
     double stall_s;           /* seconds since the worker last changed a request or batch
                                  while work was outstanding (0 when idle) */
+    double busy_s;            /* server seconds so far with at least one chunk on the GPU */
+    double slot_s;            /* slot-seconds so far: occupied slots integrated over time */
 } tm_serve_status;
 /* Copy the latest snapshot into *out.  Errors: TM_ERR_ARG. */
 int tm_serve_status_get(tm_server *srv, tm_serve_status *out);

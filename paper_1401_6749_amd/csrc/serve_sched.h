@@ -107,6 +107,10 @@ struct Sched {
     std::map<std::pair<const tm_gauge *, int>, BatchRec *> batches;  // worker only
     int worker_error = TM_OK;    // worker only (copied into snap)
     double last_progress = 0;    // worker only
+    // utilisation integrals (worker only): the state of the last snapshot
+    // holds until the next one
+    double t_pub = -1, busy_s = 0, slot_s = 0;
+    int pub_in_flight = 0, pub_slots = 0;
 
     Sched(Dev &d, char *base, size_t bytes) : dev(d) { arena.init(base, bytes); }
 
@@ -429,6 +433,15 @@ struct Sched {
             st.pending_jobs += (int)kv.second->pending.size();
             st.running_slots += dev.active(kv.second->b);
         }
+        if (t_pub >= 0 && now > t_pub) {
+            if (pub_in_flight > 0) busy_s += now - t_pub;
+            slot_s += (now - t_pub) * pub_slots;
+        }
+        t_pub = now;
+        pub_in_flight = st.in_flight;
+        pub_slots = st.running_slots;
+        st.busy_s = busy_s;
+        st.slot_s = slot_s;
         st.worker_error = worker_error;
         st.arena_used = arena.used;
         st.arena_size = arena.size;

@@ -82,7 +82,7 @@ class tm_serve_status(ctypes.Structure):
     _fields_ = [("queued", c_int), ("active", c_int), ("finished", c_int), ("batches", c_int), ("in_flight", c_int),
                 ("pending_jobs", c_int), ("running_slots", c_int), ("worker_error", c_int), ("arena_used", c_size_t),
                 ("arena_size", c_size_t), ("arena_largest_free", c_size_t), ("t_snapshot", c_double),
-                ("stall_s", c_double)]
+                ("stall_s", c_double), ("busy_s", c_double), ("slot_s", c_double)]
 
 
 class tm_tsm_stats(ctypes.Structure):

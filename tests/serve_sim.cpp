@@ -348,7 +348,8 @@ long long run(uint64_t seed, const Scenario &sc)
     std::map<uint64_t, int> seen;  // tag -> times finished
     std::vector<double> admit_order;
     std::map<uint64_t, double> t_admit;
-    double max_stall = 0;
+    double max_stall = 0, prev_busy = 0, prev_slot = 0, prev_now = dev.now, prev_cap = 0;
+    const double t_first = dev.now;
     for (;;) {
         while (next < subs.size() && subs[next].t <= dev.now) {
             const Sub &s = subs[next];
@@ -404,6 +405,18 @@ long long run(uint64_t seed, const Scenario &sc)
         {
             std::lock_guard<std::mutex> lk(Q.mu);
             max_stall = std::max(max_stall, Q.snap.stall_s);
+            // utilisation integrals: non-decreasing, busy time within the
+            // elapsed time, and since the last step at most the slots of the
+            // batches resident then, for the time since then
+            const tm_serve_status &ss = Q.snap;
+            if (ss.busy_s < prev_busy || ss.slot_s < prev_slot) fail("utilisation integrals decreased%s", "");
+            if (ss.busy_s > dev.now - t_first + 1e-9) fail("busy time beyond the elapsed time%s", "");
+            if (ss.slot_s - prev_slot > (dev.now - prev_now) * prev_cap * (1 + 1e-12) + 1e-9)
+                fail("slot-seconds beyond the slots of the batches%s", "");
+            prev_busy = ss.busy_s;
+            prev_slot = ss.slot_s;
+            prev_now = dev.now;
+            prev_cap = (double)sc.slots * (double)Q.batches.size();
         }
         if (g_fail) {
             dump(Q, dev);

@@ -112,6 +112,13 @@ def test_serving_admission_under_small_budget():
             _time.sleep(0.005)
         res = _wait_all(tm, srv, 3)
         assert all(r["status"] == 0 for r in res.values())
+        # utilisation integrals: the GPU was busy for part of the server's
+        # time; at most two requests are active, each with an HP and an LP
+        # batch of 4 slots
+        _time.sleep(0.1)
+        st = tm.tm_serve_status_get(srv)
+        assert 0.0 < st["busy_s"] <= st["t_snapshot"]
+        assert 0.0 < st["slot_s"] <= 16 * st["t_snapshot"]
         ordered = sorted(res.values(), key=lambda r: r["t_admit"])
         # later requests waited in the queue until earlier ones released their
         # workspace (only the final projection may overlap the next admission)
