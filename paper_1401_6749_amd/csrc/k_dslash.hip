@@ -170,20 +170,6 @@ struct RawZ4 {
     }
 };
 
-// the nine packed complex halves (re low, im high) of half-precision link (par, mu) of site i
-__device__ __forceinline__ void load_link_words(__amdgpu_buffer_rsrc_t rs, int vh, int par, int mu, int i,
-                                                uint32_t w[9])
-{
-    const uint32_t base = (uint32_t)(par * 4 + mu) * 36u * (uint32_t)vh;
-#pragma unroll
-    for (int g = 0; g < 2; g++) {
-        const u32x4 q = bld16(rs, (uint32_t)i * 16u, base + (uint32_t)g * 16u * (uint32_t)vh);
-#pragma unroll
-        for (int k = 0; k < 4; k++) w[4 * g + k] = q[k];
-    }
-    w[8] = bld4(rs, (uint32_t)i * 4u, base + 32u * (uint32_t)vh);
-}
-
 // link (par, mu) of site i through the gauge resource
 template <int SP, class T>
 __device__ __forceinline__ void load_link(__amdgpu_buffer_rsrc_t rs, int vh, int par, int mu, int i, Link<T> &L)
@@ -203,13 +189,27 @@ __device__ __forceinline__ void load_link(__amdgpu_buffer_rsrc_t rs, int vh, int
             L.u[(2 * g + 1) / 3][(2 * g + 1) % 3] = cpx<T>{(T)q.z, (T)q.w};
         }
     } else {
-        // all nine entries stored
+        // packed complex halves: all nine entries, or rows 0 and 1
+        const uint32_t base = (uint32_t)(par * 4 + mu) * (uint32_t)HALF_LINK_BYTES * (uint32_t)vh;
+        constexpr int NW = TM_HALF_LINK12 ? 6 : 9;
         uint32_t w[9];
-        load_link_words(rs, vh, par, mu, i, w);
+        const u32x4 q = bld16(rs, (uint32_t)i * 16u, base);
 #pragma unroll
-        for (int k = 0; k < 9; k++)
+        for (int k = 0; k < 4; k++) w[k] = q[k];
+        if constexpr (NW == 6) {
+            const u32x2 r = bld8(rs, (uint32_t)i * 8u, base + 16u * (uint32_t)vh);
+            w[4] = r[0];
+            w[5] = r[1];
+        } else {
+            const u32x4 q1 = bld16(rs, (uint32_t)i * 16u, base + 16u * (uint32_t)vh);
+#pragma unroll
+            for (int k = 0; k < 4; k++) w[4 + k] = q1[k];
+            w[8] = bld4(rs, (uint32_t)i * 4u, base + 32u * (uint32_t)vh);
+        }
+#pragma unroll
+        for (int k = 0; k < NW; k++)
             L.u[k / 3][k % 3] = cpx<T>{(T)HalfCodec<SP>::dec(w[k] & 0xFFFFu), (T)HalfCodec<SP>::dec(w[k] >> 16)};
-        return;
+        if constexpr (NW == 9) return;
     }
     rebuild_row2(L);
 }
@@ -295,6 +295,53 @@ __device__ __forceinline__ h2 as_h2(uint32_t x)
 __device__ __forceinline__ float lo_f(uint32_t x) { return (float)as_h2(x).x; }
 __device__ __forceinline__ float hi_f(uint32_t x) { return (float)as_h2(x).y; }
 
+// FP16 link (par, mu) of site i for the packed-operand transport: the
+// stored entries as packed complex halves (re low, im high), all nine or,
+// with TM_HALF_LINK12, rows 0 and 1 with row 2 rebuilt in FP32 as the
+// conjugated cross product of the two
+struct LinkPk {
+    uint32_t w[TM_HALF_LINK12 ? 6 : 9];
+    float r2[TM_HALF_LINK12 ? 6 : 1];
+};
+// entry (row, col) of a packed link as FP32 (re, im)
+__device__ __forceinline__ void link_entry(const LinkPk &L, int row, int col, float &re, float &im)
+{
+    if (TM_HALF_LINK12 != 0 && row == 2) {
+        re = L.r2[2 * col];
+        im = L.r2[2 * col + 1];
+    } else {
+        re = lo_f(L.w[3 * row + col]);
+        im = hi_f(L.w[3 * row + col]);
+    }
+}
+__device__ __forceinline__ void load_link_words(__amdgpu_buffer_rsrc_t rs, int vh, int par, int mu, int i, LinkPk &L)
+{
+    const uint32_t base = (uint32_t)(par * 4 + mu) * (uint32_t)HALF_LINK_BYTES * (uint32_t)vh;
+    const u32x4 q = bld16(rs, (uint32_t)i * 16u, base);
+#pragma unroll
+    for (int k = 0; k < 4; k++) L.w[k] = q[k];
+    if constexpr (TM_HALF_LINK12 != 0) {
+        const u32x2 r = bld8(rs, (uint32_t)i * 8u, base + 16u * (uint32_t)vh);
+        L.w[4] = r[0];
+        L.w[5] = r[1];
+        // row 2 = conj(row 0 x row 1): entry j from columns k = j+1, l = j+2 (mod 3)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const int k = (j + 1) % 3, l = (j + 2) % 3;
+            const float ar = lo_f(L.w[k]), ai = hi_f(L.w[k]), br = lo_f(L.w[3 + l]), bi = hi_f(L.w[3 + l]);
+            const float cr = lo_f(L.w[l]), ci = hi_f(L.w[l]), dr = lo_f(L.w[3 + k]), di = hi_f(L.w[3 + k]);
+            // a b - c d, then conjugated
+            L.r2[2 * j] = fmaf(ar, br, fmaf(-ai, bi, fmaf(-cr, dr, ci * di)));
+            L.r2[2 * j + 1] = -fmaf(ar, bi, fmaf(ai, br, fmaf(-cr, di, -(ci * dr))));
+        }
+    } else {
+        const u32x4 q1 = bld16(rs, (uint32_t)i * 16u, base + 16u * (uint32_t)vh);
+#pragma unroll
+        for (int k = 0; k < 4; k++) L.w[4 + k] = q1[k];
+        L.w[8] = bld4(rs, (uint32_t)i * 4u, base + 32u * (uint32_t)vh);
+    }
+}
+
 // sc times the half spinor of colour c for the projector (1 + S g_mu), FP32,
 // from the stored words p[3*spin + colour]: two mixed-precision FMAs per real
 // component, so the neighbour's scale costs nothing later
@@ -318,17 +365,18 @@ __device__ __forceinline__ void project_pk(const uint32_t p[12], int c, float sc
     }
 }
 
-// w = U h (FWD) or U^dagger h from the link words u[3*row + col]
+// w = U h (FWD) or U^dagger h from the link entries
 template <bool FWD>
-__device__ __forceinline__ void transport_pk(const uint32_t u[9], const cpx<float> h[3], float wr[3], float wi[3])
+__device__ __forceinline__ void transport_pk(const LinkPk &u, const cpx<float> h[3], float wr[3], float wi[3])
 {
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         float re = 0.f, im = 0.f;
 #pragma unroll
         for (int b = 0; b < 3; b++) {
-            const uint32_t e = FWD ? u[3 * a + b] : u[3 * b + a];
-            const float ur = lo_f(e), ui = FWD ? hi_f(e) : -hi_f(e);
+            float ur, ui;
+            link_entry(u, FWD ? a : b, FWD ? b : a, ur, ui);
+            if (!FWD) ui = -ui;
             re = fmaf(ur, h[b].re, fmaf(-ui, h[b].im, re));
             im = fmaf(ur, h[b].im, fmaf(ui, h[b].re, im));
         }
@@ -349,7 +397,7 @@ __device__ __forceinline__ void hop_compute_pk(const DslashArgs &A, __amdgpu_buf
 #pragma unroll
     for (int k = 0; k < 12; k++) p[k] = raw.q[k >> 2][k & 3];
     float sc = raw.sc;
-    uint32_t u[9];
+    LinkPk u;
     load_link_words(gauge, vh, FWD ? A.out_par : 1 - A.out_par, MU, FWD ? s.cb : n, u);
     if (MU == 3 && A.g.tbc < 0 && s.t == (FWD ? A.g.L[3] - 1 : 0)) sc = -sc;
     cpx<float> h0[3], h1[3];
@@ -969,7 +1017,7 @@ static bool launch_walk(DslashArgs A, hipStream_t s)
         A.twalk = tw;
         A.in_span = (uint32_t)field;
         A.gauge_span = (uint32_t)std::min<uint64_t>(
-            (uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : SP == P32 ? 48 : 36), 0xFFFFFFFFull);
+            (uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : SP == P32 ? 48 : HALF_LINK_BYTES), 0xFFFFFFFFull);
         static const int gouter = env_knob("TM_GROUP_OUTER", 0);
         A.gouter = gouter;
         const int cs = A.wcy * A.wcz * A.g.lxh;
@@ -998,7 +1046,7 @@ static void launch_t(DslashArgs A, hipStream_t s)
     const uint64_t field = (uint64_t)A.g.vh * (SP == P64 ? 192 : SP == P32 ? 96 : 52);
     if (R > 1 && ((uint64_t)(R - 1) * A.in_slot + field >= (1ull << 32) || A.in_slot % 16)) R = 1;
     A.in_span = (uint32_t)std::min<uint64_t>((uint64_t)(R - 1) * A.in_slot + field, 0xFFFFFFFFull);
-    A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : SP == P32 ? 48 : 36),
+    A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : SP == P32 ? 48 : HALF_LINK_BYTES),
                                                 0xFFFFFFFFull);
     const int spb = BLOCK / R;
     int tw = dslash_twalk();

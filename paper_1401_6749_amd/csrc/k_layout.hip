@@ -26,16 +26,21 @@ __global__ __launch_bounds__(BLOCK) void k_gauge_pack(Geom g, const double *cano
                 o[(size_t)q * g.vh + cb] = make_float4((float)u[2 * q].x, (float)u[2 * q].y, (float)u[2 * q + 1].x,
                                                        (float)u[2 * q + 1].y);
         } else {
-            // all nine entries: [uint4 entries 0..3][uint4 entries 4..7][uint entry 8], each [Vh]
-            char *o = (char *)out + base * 36 * g.vh;
+            // packed complex halves in the layout LinkHalfIO reads (nine
+            // entries, or the first two rows with TM_HALF_LINK12)
+            char *o = (char *)out + base * HALF_LINK_BYTES * g.vh;
             uint32_t w[9];
             for (int k = 0; k < 9; k++) {
                 const uint32_t lo = HalfCodec<P>::enc((float)u[k].x), hi = HalfCodec<P>::enc((float)u[k].y);
                 w[k] = lo | (hi << 16);
             }
-            for (int q = 0; q < 2; q++)
-                ((uint4 *)o)[(size_t)q * g.vh + cb] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-            ((uint32_t *)(o + (size_t)32 * g.vh))[cb] = w[8];
+            ((uint4 *)o)[cb] = make_uint4(w[0], w[1], w[2], w[3]);
+            if constexpr (TM_HALF_LINK12 != 0) {
+                ((uint2 *)(o + (size_t)16 * g.vh))[cb] = make_uint2(w[4], w[5]);
+            } else {
+                ((uint4 *)o)[(size_t)g.vh + cb] = make_uint4(w[4], w[5], w[6], w[7]);
+                ((uint32_t *)(o + (size_t)32 * g.vh))[cb] = w[8];
+            }
         }
     }
 }

@@ -274,7 +274,7 @@ template <>
 struct SpinorIO<PBF> : SpinorHalfIO<PBF> {};
 
 __host__ __device__ constexpr size_t spinor_site_bytes(int p) { return p == P64 ? 192 : p == P32 ? 96 : 52; }
-__host__ __device__ constexpr size_t link_bytes(int p) { return p == P64 ? 96 : p == P32 ? 48 : 36; }
+__host__ __device__ constexpr size_t link_bytes(int p) { return p == P64 ? 96 : p == P32 ? 48 : HALF_LINK_BYTES; }
 
 // ---------------------------------------------------------------------------
 // Links.  P64/P32: first two rows (12 reals) per link, third row rebuilt as
@@ -341,7 +341,17 @@ struct LinkHalfIO {
     template <class T>
     __device__ static __forceinline__ void load(const void *G, int vh, int par, int mu, int i, Link<T> &L)
     {
-        const char *base = (const char *)G + (size_t)(par * 4 + mu) * 36 * vh;
+        const char *base = (const char *)G + (size_t)(par * 4 + mu) * HALF_LINK_BYTES * vh;
+        if constexpr (TM_HALF_LINK12 != 0) {
+            const uint4 q = ((const uint4 *)base)[i];
+            const uint2 r = ((const uint2 *)(base + (size_t)16 * vh))[i];
+            const uint32_t w[6] = {q.x, q.y, q.z, q.w, r.x, r.y};
+#pragma unroll
+            for (int k = 0; k < 6; k++)
+                L.u[k / 3][k % 3] = cpx<T>{(T)HalfCodec<P>::dec(w[k] & 0xFFFFu), (T)HalfCodec<P>::dec(w[k] >> 16)};
+            rebuild_row2(L);
+            return;
+        }
         uint32_t w[9];
 #pragma unroll
         for (int g = 0; g < 2; g++) {

@@ -134,7 +134,7 @@ __host__ __device__ inline size_t half_bytes(int p, const Geom &g)
 }
 inline size_t link_array_bytes(int p, const Geom &g)
 {
-    return (size_t)2 * 4 * g.vh * (p == P64 ? 96 : p == P32 ? 48 : 36);
+    return (size_t)2 * 4 * g.vh * (p == P64 ? 96 : p == P32 ? 48 : HALF_LINK_BYTES);
 }
 __host__ __device__ inline int nblk_of(const Geom &g) { return (g.vh + BLOCK - 1) / BLOCK; }
 // per-slot partial sums: one per 64-site tile

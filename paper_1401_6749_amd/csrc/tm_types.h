@@ -5,6 +5,15 @@
 
 namespace tmk {
 
+// Half-precision links: all nine entries (36 B: [uint4 entries 0..3][uint4
+// entries 4..7][uint entry 8], each [Vh]) or, with TM_HALF_LINK12, the first
+// two rows (24 B: [uint4 entries 0..3][uint2 entries 4..5]) with the third
+// rebuilt in FP32 at every load.
+#ifndef TM_HALF_LINK12
+#define TM_HALF_LINK12 0
+#endif
+constexpr int HALF_LINK_BYTES = TM_HALF_LINK12 ? 24 : 36;
+
 // storage precision index (kernel templates); tm_prec bit = 1 << index
 enum : int { P64 = 0, P32 = 1, P16 = 2, PBF = 3 };
 
