@@ -31,6 +31,11 @@
  * pointers are ordinary host memory.  The caller owns every buffer it
  * passes; the library owns contexts, gauge handles and serving engines
  * until the matching destroy/free call.
+ * Threads: calls on one context must not overlap in time from several host
+ * threads, except tm_serve_submit, tm_serve_poll, tm_serve_status_get,
+ * tm_serve_clock, tm_serve_drain, tm_serve_footprint, tm_last_error and
+ * tm_memory_usage, which may run while a serving engine's worker thread
+ * uses the context.
  */
 #ifndef TM_H
 #define TM_H
@@ -109,7 +114,8 @@ int tm_create(int device, size_t hbm_budget, tm_alloc_fn alloc, tm_free_fn free_
 /* Release every gauge field and workspace of the context, then the context. */
 int tm_destroy(tm_context *ctx);
 
-/* Message of the last failing call on ctx (owned by ctx; "" if none). */
+/* Message of the last failing call on ctx ("" if none), copied for the calling
+ * thread: valid until that thread's next tm_last_error call. */
 const char *tm_last_error(const tm_context *ctx);
 
 /* Bytes currently held on the device by ctx, and the peak since creation. */

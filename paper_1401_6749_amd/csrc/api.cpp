@@ -240,11 +240,21 @@ extern "C" int tm_destroy(tm_context *ctx)
     return TM_OK;
 }
 
-extern "C" const char *tm_last_error(const tm_context *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+// The message is copied under the context lock into a per-thread buffer: a
+// serving worker may set a new message on the context at any time.
+extern "C" const char *tm_last_error(const tm_context *ctx)
+{
+    if (!ctx) return "null context";
+    thread_local std::string copy;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    copy = ctx->err;
+    return copy.c_str();
+}
 
 extern "C" int tm_memory_usage(const tm_context *ctx, size_t *in_use, size_t *peak)
 {
     if (!ctx) return TM_ERR_ARG;
+    std::lock_guard<std::mutex> lk(ctx->mu);
     if (in_use) *in_use = ctx->in_use;
     if (peak) *peak = ctx->peak;
     return TM_OK;

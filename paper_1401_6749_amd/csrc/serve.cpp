@@ -286,9 +286,14 @@ extern "C" int tm_serve_poll(tm_server *S, tm_result *out, int max)
             r.est = (double *)malloc(2 * nops * sizeof(double));
             r.var_re = (double *)malloc(nops * sizeof(double));
             r.var_im = (double *)malloc(nops * sizeof(double));
-            std::memcpy(r.est, R->res.data(), 2 * nops * sizeof(double));
-            std::memcpy(r.var_re, R->res.data() + 2 * nops, nops * sizeof(double));
-            std::memcpy(r.var_im, R->res.data() + 3 * nops, nops * sizeof(double));
+            if (r.est && r.var_re && r.var_im) {
+                std::memcpy(r.est, R->res.data(), 2 * nops * sizeof(double));
+                std::memcpy(r.var_re, R->res.data() + 2 * nops, nops * sizeof(double));
+                std::memcpy(r.var_im, R->res.data() + 3 * nops, nops * sizeof(double));
+            } else {
+                tm_result_free(&r);
+                r.status = TM_ERR_NOMEM;
+            }
         }
         for (Job &j : R->hp) {
             r.stats.hp_solves++;

@@ -23,11 +23,11 @@ struct tm_context {
     tm_alloc_fn alloc = nullptr;
     tm_free_fn free_fn = nullptr;
     void *user = nullptr;
-    std::mutex mu;  // allocation table and error string
+    mutable std::mutex mu;  // allocation table and error string
     std::unordered_map<void *, size_t> allocs;
     std::string err;
     int swz = 1;         // XCD-aware block mapping
-    int use_graphs = 1;  // capture CG chunks in hipGraphs
+    std::atomic<int> use_graphs{1};  // capture CG chunks in hipGraphs (a serving worker may clear it)
     // scratch of tm_dslash (grown on demand)
     void *op_tmp = nullptr;
     size_t op_tmp_bytes = 0;
