@@ -168,7 +168,11 @@ int tm_field_export(tm_context *ctx, const tm_gauge *gauge, tm_prec prec, int nr
 /* Apply op to nrhs fields in the device layout of prec (full-lattice
  * fields for HOP/M/MDAG, even-half fields for the MHAT family), fields
  * contiguous one after another.  kappa and two_kappa_mu = a as in M above.
- * in and out must not overlap.  Asynchronous on hip_stream; no host sync.
+ * in and out must not overlap.  Asynchronous on hip_stream; no host sync,
+ * except that the MHAT family takes its temporaries (one even-odd half
+ * field per rhs, two for MHAT_DAG_MHAT) from the context, grown on demand
+ * with a device synchronisation; MHAT-family calls on one context that
+ * overlap on different streams race on them.
  * Errors: TM_ERR_ARG (nrhs < 1 or > 16, aliasing, prec not loaded). */
 int tm_dslash(tm_context *ctx, const tm_gauge *gauge, tm_op op, double kappa, double two_kappa_mu,
               tm_prec prec, int nrhs, const void *in, void *out, void *hip_stream);
@@ -380,7 +384,8 @@ int tm_loops_tdil(tm_context *ctx, const tm_gauge *gauge, const tm_tsm_params *p
  *   src_ids  host, n source ids;  raw  device, n * 9 * Lt * 32 doubles
  *   n        1..16
  * Asynchronous on hip_stream.  Its scratch (Z4 codes, partial sums) is the
- * context's, grown on demand (with a device synchronisation).  Errors:
+ * context's, grown on demand (with a device synchronisation): calls on one
+ * context that overlap on different streams race on it.  Errors:
  * TM_ERR_ARG, TM_ERR_NOMEM, TM_ERR_HIP. */
 int tm_contract(tm_context *ctx, const tm_gauge *gauge, tm_prec prec, int n, const void *s, size_t s_stride,
                 uint64_t noise_seed, const uint64_t *src_ids, double *raw, void *hip_stream);
