@@ -338,6 +338,60 @@ def write_traffic(fetch_db: str, write_db: str, workload: str) -> None:
     print(json.dumps(out))
 
 
+def counter_summary(out_json: str, kernel: str, bench_args: str, dbs, sites: int, sources: int) -> None:
+    """Per-dispatch means of every counter that the rocprofv3 --pmc databases
+    `dbs` hold for the kernels whose name contains `kernel`, with FETCH_SIZE
+    and WRITE_SIZE turned into bytes by what the same counters read for the
+    1 GiB streaming copy in the same run, and, where the counters are there,
+    the VALU issue share (a wave64 VALU instruction takes four cycles of one
+    of the 1024 SIMDs; GRBM_GUI_ACTIVE sums the cycles of the 8 XCDs) and the
+    VALU lane instructions per site and source."""
+    import sqlite3
+
+    means, copy, commands, n = {}, {}, [], {}
+    for db in dbs:
+        cur = sqlite3.connect(db).cursor()
+        rows = cur.execute("select kernel_name, counter_name, value from counters_collection").fetchall()
+        names = sorted({c for _, c, _ in rows})
+        for c in names:
+            kv = [v for k, cn, v in rows if cn == c and kernel in k]
+            cv = [v for k, cn, v in rows if cn == c and "k_stream_copy" in k]
+            if kv:
+                means[c] = sum(kv) / len(kv)
+                n[c] = len(kv)
+            if cv:
+                copy[c] = sum(cv) / len(cv)
+        commands.append(f"rocprofv3 --pmc {' '.join(names)} -d {os.path.dirname(db)} -o "
+                        f"{os.path.basename(db).split('_results')[0]} -- python3 bench.py {bench_args}")
+    if not means:
+        raise SystemExit(f"no counter rows for kernels containing {kernel!r}")
+    out = {"kernel": kernel, "bench_args": bench_args, "dispatches": n, "per_dispatch_means": means,
+           "copy_kernel_per_dispatch_means": copy, "derived": {}}
+    d = out["derived"]
+    if "FETCH_SIZE" in means and "FETCH_SIZE" in copy:
+        d["fetch_scale"] = round((1 << 30) / (copy["FETCH_SIZE"] * 1024.0), 4)
+        d["fetch_bytes_per_dispatch"] = round(means["FETCH_SIZE"] * 1024.0 * d["fetch_scale"])
+    if "WRITE_SIZE" in means and "WRITE_SIZE" in copy:
+        d["write_scale"] = round((1 << 30) / (copy["WRITE_SIZE"] * 1024.0), 4)
+        d["write_bytes_per_dispatch"] = round(means["WRITE_SIZE"] * 1024.0 * d["write_scale"])
+    if "SQ_INSTS_VALU" in means and "GRBM_GUI_ACTIVE" in means:
+        cyc = means["GRBM_GUI_ACTIVE"] / 8.0
+        d["gpu_cycles_per_xcd"] = round(cyc)
+        d["valu_issue_busy"] = round(means["SQ_INSTS_VALU"] * 4.0 / (1024.0 * cyc), 3)
+        d["valu_lane_instructions_per_site_source"] = round(means["SQ_INSTS_VALU"] * 64.0 / (sites * sources), 1)
+    if "TCC_HIT_sum" in means and "TCC_MISS_sum" in means:
+        d["l2_hit_rate"] = round(means["TCC_HIT_sum"] / (means["TCC_HIT_sum"] + means["TCC_MISS_sum"]), 3)
+    out["sites_per_dispatch"] = sites
+    out["sources_per_dispatch"] = sources
+    commands.append(f"python3 bench.py --counter-summary {out_json} '{kernel}' {bench_args.lstrip('-')} " +
+                    " ".join(dbs))
+    out["commands"] = commands
+    with open(out_json, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
 def trace_summary(trace_dir: str, command: str, top: int = 40) -> str:
     """Text summary of a rocprofv3 --kernel-trace --stats --output-format csv
     run: per kernel calls, total / average / min / max duration, share of the
@@ -735,6 +789,11 @@ def main():
     ap.add_argument("--trace-summary", nargs=3, metavar=("TRACE_DIR", "OUT_TXT", "COMMAND"),
                     help="write a text summary of a rocprofv3 --kernel-trace --stats --output-format csv run "
                          "(the command that produced it as the third argument) and exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar="ARG",
+                    help="OUT_JSON KERNEL MODE DB [DB ...]: per-dispatch counter means of the kernels whose "
+                         "name contains KERNEL in rocprofv3 --pmc databases of `bench.py --MODE` runs (MODE "
+                         "contract-only or roofline-only; 32^3x64, 12 sources per dispatch), written to OUT_JSON, "
+                         "and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the roofline kernel's HBM traffic from two rocprofv3 --pmc databases "
                          "(FETCH_SIZE, WRITE_SIZE) of --roofline-only runs and exit")
@@ -747,6 +806,17 @@ def main():
         return
     if args.traffic_from:
         write_traffic(args.traffic_from[0], args.traffic_from[1], args.workload)
+        return
+    if args.counter_summary:
+        if len(args.counter_summary) < 4:
+            ap.error("--counter-summary needs OUT_JSON KERNEL MODE DB [DB ...]")
+        o, k, mode = args.counter_summary[:3]
+        if mode not in ("contract-only", "roofline-only"):
+            ap.error("--counter-summary: MODE is contract-only or roofline-only")
+        b = "--" + mode
+        Wc = WORKLOADS[args.workload]
+        d0, d1, d2, d3 = Wc["dims"]
+        counter_summary(o, k, b, args.counter_summary[3:], sites=d0 * d1 * d2 * d3, sources=Wc["batch"])
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the whole lattice is resident on a single MI355X and this build "
@@ -773,6 +843,14 @@ def main():
             out = {"roofline": measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)}
         else:
             out = {"contraction_rates": contract_rates(torch, tm, inputs, ctx, g, W)}
+            # the copy kernel calibrates FETCH_SIZE / WRITE_SIZE in counter runs of this mode
+            nb = 1 << 30
+            ca = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            cb = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            for _ in range(4):
+                tm.tm_stream_copy(ctx, ca, cb, nb)
+            torch.cuda.synchronize()
+            del ca, cb
         print(json.dumps(out), flush=True)
         tm.tm_free_gauge(ctx, g)
         tm.tm_destroy(ctx)

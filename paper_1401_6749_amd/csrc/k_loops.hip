@@ -144,24 +144,88 @@ __device__ __forceinline__ bool contract_site(const Geom &g, int t, int q, int &
     return true;
 }
 
+// Arithmetic of the contraction as explicit multiply-add chains: a colour
+// sum of three complex products is one multiply and five multiply-adds per
+// real part (written as sums of separate products, each needs two more
+// instructions).
+template <class T>
+__device__ __forceinline__ T tfma(T a, T b, T c)
+{
+    if constexpr (sizeof(T) == 8) return fma(a, b, c);
+    else return fmaf(a, b, c);
+}
+// sum_c conj(l[c * sl]) w[c * sw], c = 0..2
+template <class T>
+__device__ __forceinline__ cpx<T> cdot3(const cpx<T> *l, int sl, const cpx<T> *w, int sw)
+{
+    T re = l[0].re * w[0].re, im = l[0].re * w[0].im;
+    re = tfma(l[0].im, w[0].im, re);
+    im = tfma(-l[0].im, w[0].re, im);
+#pragma unroll
+    for (int c = 1; c < 3; c++) {
+        const cpx<T> a = l[c * sl], b = w[c * sw];
+        re = tfma(a.re, b.re, re);
+        re = tfma(a.im, b.im, re);
+        im = tfma(a.re, b.im, im);
+        im = tfma(-a.im, b.re, im);
+    }
+    return {re, im};
+}
+// o = U h (colour vectors), U's rows as multiply-add chains
+template <class T>
+__device__ __forceinline__ void umul_chain(const Link<T> &L, const cpx<T> h[3], cpx<T> o[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const cpx<T> u0 = L.u[a][0];
+        T re = u0.re * h[0].re, im = u0.re * h[0].im;
+        re = tfma(-u0.im, h[0].im, re);
+        im = tfma(u0.im, h[0].re, im);
+#pragma unroll
+        for (int b = 1; b < 3; b++) {
+            const cpx<T> u = L.u[a][b];
+            re = tfma(u.re, h[b].re, re);
+            re = tfma(-u.im, h[b].im, re);
+            im = tfma(u.re, h[b].im, im);
+            im = tfma(u.im, h[b].re, im);
+        }
+        o[a] = {re, im};
+    }
+}
+
 // One kind of spin matrix for the thread's sites, 32 FP64 accumulators:
 //   KIND 0: local; KIND 1+nu: F^nu; KIND 5+nu: B^nu.
 // Products in the precision of s (FP64 for HP and FP64 solves, FP32 for LP
 // solves, with links of the same precision); sums always in FP64.
-// left vector: Z4 codes (unscaled noise) or a field of precision SPS
+// left vector: Z4 codes (unscaled noise) or a field of precision SPS.  The
+// antiperiodic sign of a hop across the time boundary multiplies the noise:
+// for codes it flips their 24 sign bits (the code itself), for a field it
+// multiplies the transported vector.
 template <int SPS, bool FIELD>
 struct LeftVec {
     const uint32_t *codes;
     const char *fld[2];
+    // unscaled Z4 value of component k: (+-1, +-1), (0, 0) at flagged sites
     template <class T>
-    __device__ __forceinline__ void get(const Geom &g, int par, int cb, cpx<T> l[12]) const
+    __device__ static __forceinline__ T z4_part(uint32_t c, int bit, uint32_t one_hi)
+    {
+        const uint32_t sgn = (c << (31 - bit)) & 0x80000000u;
+        if constexpr (sizeof(T) == 8) return __hiloint2double((int)(sgn | one_hi), 0);
+        else return __uint_as_float(sgn | one_hi);
+    }
+    template <class T>
+    __device__ __forceinline__ void get(const Geom &g, int par, int cb, cpx<T> l[12], bool neg = false) const
     {
         if constexpr (FIELD) {
             SpinorIO<SPS>::load(fld[par], g.vh, cb, l);
         } else {
-            const uint32_t c = codes[(size_t)par * g.vh + cb];
+            uint32_t c = codes[(size_t)par * g.vh + cb];
+            const bool zero = (c & Z4_ZERO) != 0;
+            if (neg) c ^= 0x00FFFFFFu;
+            // high word of 1.0 (FP64) or its bits (FP32); zero at flagged sites
+            const uint32_t one_hi = zero ? 0u : (sizeof(T) == 8 ? 0x3FF00000u : 0x3F800000u);
 #pragma unroll
-            for (int k = 0; k < 12; k++) l[k] = z4_unscaled<T>(c, k);
+            for (int k = 0; k < 12; k++) l[k] = cpx<T>{z4_part<T>(c, 2 * k, one_hi), z4_part<T>(c, 2 * k + 1, one_hi)};
         }
     }
 };
@@ -186,8 +250,7 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
             for (int a = 0; a < 4; a++)
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
-                    cpx<T> f = cmulc(lv[3 * a], sv[3 * b]) + cmulc(lv[3 * a + 1], sv[3 * b + 1]) +
-                               cmulc(lv[3 * a + 2], sv[3 * b + 2]);
+                    const cpx<T> f = cdot3(&lv[3 * a], 1, &sv[3 * b], 1);
                     acc[2 * (4 * a + b)] += (double)f.re;
                     acc[2 * (4 * a + b) + 1] += (double)f.im;
                 }
@@ -197,41 +260,43 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
             const int nf = nbr<NU, 1>(g, s);
             Link<T> L;
             LinkIO<SPS>::load(G, g.vh, par, NU, cb, L);
-            const T sg = (NU == 3 && g.tbc < 0 && s.t == g.L[3] - 1) ? (T)-1 : (T)1;
+            const bool neg = NU == 3 && g.tbc < 0 && s.t == g.L[3] - 1;
             if constexpr (KIND <= 4) {
-                // F: conj(l_a(x)) . (U s(x+nu))_b
+                // F: conj(l_a(x)) . (U s(x+nu))_b, the boundary sign on l
                 cpx<T> lv[12], snb[12];
-                left.get(g, par, cb, lv);
+                left.get(g, par, cb, lv, !FIELD && neg);
                 SpinorIO<SPS>::load(s_fld[1 - par], g.vh, nf, snb);
 #pragma unroll
                 for (int b = 0; b < 4; b++) {
-                    cpx<T> h[3], w[3];
+                    cpx<T> w[3];
+                    umul_chain(L, &snb[3 * b], w);
+                    if (FIELD && neg) {
 #pragma unroll
-                    for (int c = 0; c < 3; c++) h[c] = cpx<T>{sg * snb[3 * b + c].re, sg * snb[3 * b + c].im};
-                    umul(L, h, w);
+                        for (int c = 0; c < 3; c++) w[c] = cpx<T>{-w[c].re, -w[c].im};
+                    }
 #pragma unroll
                     for (int a = 0; a < 4; a++) {
-                        cpx<T> f = cmulc(lv[3 * a], w[0]) + cmulc(lv[3 * a + 1], w[1]) + cmulc(lv[3 * a + 2], w[2]);
+                        const cpx<T> f = cdot3(&lv[3 * a], 1, w, 1);
                         acc[2 * (4 * a + b)] += (double)f.re;
                         acc[2 * (4 * a + b) + 1] += (double)f.im;
                     }
                 }
             } else {
-                // B: conj((U l(x+nu))_a) . s_b(x)
+                // B: conj((U l(x+nu))_a) . s_b(x), the boundary sign on l
                 cpx<T> lf[12], sv[12];
-                left.get(g, 1 - par, nf, lf);
+                left.get(g, 1 - par, nf, lf, !FIELD && neg);
                 SpinorIO<SPS>::load(s_fld[par], g.vh, cb, sv);
 #pragma unroll
                 for (int a = 0; a < 4; a++) {
-                    cpx<T> e[3], v[3];
+                    cpx<T> v[3];
+                    umul_chain(L, &lf[3 * a], v);
+                    if (FIELD && neg) {
 #pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        e[c] = cpx<T>{sg * lf[3 * a + c].re, sg * lf[3 * a + c].im};
+                        for (int c = 0; c < 3; c++) v[c] = cpx<T>{-v[c].re, -v[c].im};
                     }
-                    umul(L, e, v);
 #pragma unroll
                     for (int b = 0; b < 4; b++) {
-                        cpx<T> f = cmulc(v[0], sv[3 * b]) + cmulc(v[1], sv[3 * b + 1]) + cmulc(v[2], sv[3 * b + 2]);
+                        const cpx<T> f = cdot3(v, 1, &sv[3 * b], 1);
                         acc[2 * (4 * a + b)] += (double)f.re;
                         acc[2 * (4 * a + b) + 1] += (double)f.im;
                     }
