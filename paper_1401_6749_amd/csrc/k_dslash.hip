@@ -235,25 +235,38 @@ __device__ __forceinline__ void project_c(const R &raw, int c, cpx<T> &h0, cpx<T
 }
 
 // w = U h (FWD) or U^dagger h, accumulated colour by colour of h
+// entry a of U h (FWD) or U^dagger h as two multiply-add chains: one
+// multiply and five multiply-adds per real part
+template <class T, bool FWD>
+__device__ __forceinline__ cpx<T> link_row(const Link<T> &L, int a, const cpx<T> h[3])
+{
+    T re = 0, im = 0;
+#pragma unroll
+    for (int b = 0; b < 3; b++) {
+        const cpx<T> u = FWD ? L.u[a][b] : L.u[b][a];
+        const T ui = FWD ? u.im : -u.im;
+        if (b == 0) {
+            re = u.re * h[0].re;
+            im = u.re * h[0].im;
+        } else {
+            re = fma(u.re, h[b].re, re);
+            im = fma(u.re, h[b].im, im);
+        }
+        re = fma(-ui, h[b].im, re);
+        im = fma(ui, h[b].re, im);
+    }
+    return {re, im};
+}
 template <class T, int MU, int S, bool FWD, class R>
 __device__ __forceinline__ void transport(const Link<T> &L, const R &raw, cpx<T> w[6])
 {
+    cpx<T> h0[3], h1[3];
 #pragma unroll
-    for (int k = 0; k < 6; k++) w[k] = cpx<T>{(T)0, (T)0};
+    for (int b = 0; b < 3; b++) project_c<T, MU, S>(raw, b, h0[b], h1[b]);
 #pragma unroll
-    for (int b = 0; b < 3; b++) {
-        cpx<T> h0, h1;
-        project_c<T, MU, S>(raw, b, h0, h1);
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            if (FWD) {
-                w[a] = w[a] + cmul(L.u[a][b], h0);
-                w[3 + a] = w[3 + a] + cmul(L.u[a][b], h1);
-            } else {
-                w[a] = w[a] + cmulc(L.u[b][a], h0);
-                w[3 + a] = w[3 + a] + cmulc(L.u[b][a], h1);
-            }
-        }
+    for (int a = 0; a < 3; a++) {
+        w[a] = link_row<T, FWD>(L, a, h0);
+        w[3 + a] = link_row<T, FWD>(L, a, h1);
     }
 }
 

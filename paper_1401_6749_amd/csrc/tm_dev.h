@@ -295,13 +295,21 @@ template <class T>
 __device__ __forceinline__ void rebuild_row2(Link<T> &L)
 {
     const cpx<T> *a = L.u[0], *b = L.u[1];
-    // row2 = conj(a x b)
-    cpx<T> c0 = cmul(a[1], b[2]) - cmul(a[2], b[1]);
-    cpx<T> c1 = cmul(a[2], b[0]) - cmul(a[0], b[2]);
-    cpx<T> c2 = cmul(a[0], b[1]) - cmul(a[1], b[0]);
-    L.u[2][0] = cpx<T>{c0.re, -c0.im};
-    L.u[2][1] = cpx<T>{c1.re, -c1.im};
-    L.u[2][2] = cpx<T>{c2.re, -c2.im};
+    // row2 = conj(a x b): entry j = conj(a_k b_l - a_l b_k), (j, k, l) cyclic,
+    // each real part one multiply and three multiply-adds
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        const int k = (j + 1) % 3, l = (j + 2) % 3;
+        const cpx<T> p = a[k], q = b[l], r = a[l], t = b[k];
+        T re = p.re * q.re, im = p.re * q.im;
+        re = fma(-p.im, q.im, re);
+        re = fma(-r.re, t.re, re);
+        re = fma(r.im, t.im, re);
+        im = fma(p.im, q.re, im);
+        im = fma(-r.re, t.im, im);
+        im = fma(-r.im, t.re, im);
+        L.u[2][j] = cpx<T>{re, -im};
+    }
 }
 
 template <int P>
