@@ -792,8 +792,8 @@ def main():
     ap.add_argument("--counter-summary", nargs="+", metavar="ARG",
                     help="OUT_JSON KERNEL MODE DB [DB ...]: per-dispatch counter means of the kernels whose "
                          "name contains KERNEL in rocprofv3 --pmc databases of `bench.py --MODE` runs (MODE "
-                         "contract-only or roofline-only; 32^3x64, 12 sources per dispatch), written to OUT_JSON, "
-                         "and exit")
+                         "contract-only: 12 sources over the whole 32^3x64 lattice per dispatch; roofline-only: "
+                         "12 right-hand sides over one parity), written to OUT_JSON, and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="write the roofline kernel's HBM traffic from two rocprofv3 --pmc databases "
                          "(FETCH_SIZE, WRITE_SIZE) of --roofline-only runs and exit")
@@ -816,7 +816,9 @@ def main():
         b = "--" + mode
         Wc = WORKLOADS[args.workload]
         d0, d1, d2, d3 = Wc["dims"]
-        counter_summary(o, k, b, args.counter_summary[3:], sites=d0 * d1 * d2 * d3, sources=Wc["batch"])
+        # a contraction dispatch covers the whole lattice, a hop dispatch one parity
+        sites = d0 * d1 * d2 * d3 // (2 if mode == "roofline-only" else 1)
+        counter_summary(o, k, b, args.counter_summary[3:], sites=sites, sources=Wc["batch"])
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the whole lattice is resident on a single MI355X and this build "
