@@ -369,16 +369,20 @@ static void fill_noise_run(Batch *b, int s0, int n, Job *const *jobs, int pp)
         P.delta2[i] = delta * delta;
     }
     launch_z4_codes(g, Z, n, b->codes + (size_t)s0 * 2 * g.vh, s);
-    const size_t w = n > 1 ? b->wpitch : half_bytes(pp, g);
+    // LP runs prepare their right-hand side in the solve's own half precision
+    // (FP32 arithmetic): bhat and A^-dag D bhat stored like the CG vectors
+    const bool half = !mixed && pp == P32 && b->xr == b->sp && b->hxr == b->hsp && (b->xr == P16 || b->xr == PBF);
+    const int pq = half ? b->sp : pp;
+    const size_t w = n > 1 ? b->wpitch : half_bytes(pq, g);
     char *Be = b->FB, *To = b->FC, *Ce = b->FA;
     double *part = b->partial + (size_t)s0 * b->nblk;
-    dsl_codes_run(b, pp, 3, CM_PREP, 0, s0, n, nullptr, 0, Be, w, kappa, a);
-    dsl_run(b, pp, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, w, nullptr, 0, To, w, kappa, a, n);
+    dsl_codes_run(b, pq, 3, CM_PREP, 0, s0, n, nullptr, 0, Be, w, kappa, a);
+    dsl_run(b, pq, true, EPI_PLAIN, CM_AINV_DAG, 1, Be, w, nullptr, 0, To, w, kappa, a, n);
     // LP runs: the last preparation Dslash writes r = p = rhs and x = 0 in
-    // half precision itself (same bits as the FP32 rhs converted after it)
+    // half precision itself (same bits as the rhs converted after it)
     bool fused = false;
-    if (!mixed && pp == P32 && b->xr == b->sp && b->hxr == b->hsp && (b->xr == P16 || b->xr == PBF)) {
-        DslashArgs A = dargs(b, pp);
+    if (half) {
+        DslashArgs A = dargs(b, pq);
         A.nslot = n;
         A.in = To;
         A.in_slot = w;
@@ -394,17 +398,17 @@ static void fill_noise_run(Batch *b, int s0, int n, Job *const *jobs, int pp)
         A.kappa_u = kappa;
         A.a_u = a;
         A.partial = part;
-        fused = launch_dslash_start(b->xr, A, s) == 0;
+        fused = launch_dslash_start(pq, b->xr, A, s) == 0;
     }
-    if (!fused) dsl_run(b, pp, true, EPI_NORM, CM_MHAT_DAG, 0, To, w, Be, w, Ce, w, kappa, a, n, part);
+    if (!fused) dsl_run(b, pq, true, EPI_NORM, CM_MHAT_DAG, 0, To, w, Be, w, Ce, w, kappa, a, n, part);
     launch_slot_start(b->st + s0, part, b->nblk, P, n, s);
     if (!fused) {
-        if (b->xr == b->sp && b->hxr == b->hsp) {
-            launch_cg_start(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->p + s0 * b->hsp, b->x + s0 * b->hxr, b->hxr,
+        if (b->xr == b->sp && b->hxr == b->hsp && (pq == P64 || pq == P32)) {
+            launch_cg_start(pq, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->p + s0 * b->hsp, b->x + s0 * b->hxr, b->hxr,
                             n, s);
         } else {
-            launch_convert(pp, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->hxr, n, s);
-            launch_convert(pp, b->sp, g, Ce, w, b->p + s0 * b->hsp, b->hsp, n, s);
+            launch_convert(pq, b->xr, g, Ce, w, b->r + s0 * b->hxr, b->hxr, n, s);
+            launch_convert(pq, b->sp, g, Ce, w, b->p + s0 * b->hsp, b->hsp, n, s);
             launch_zero(b->xr, g, b->x + s0 * b->hxr, b->hxr, n, s);
         }
     }

@@ -1108,8 +1108,8 @@ static void launch_src(DslashArgs A, hipStream_t s)
     A.gouter = 0;
     A.nblk_site = (A.g.vh + BLOCK - 1) / BLOCK;
     A.ntile = ntile_of(A.g);
-    A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * (SP == P64 ? 96 : 48), 0xFFFFFFFFull);
-    A.in_span = (uint32_t)std::min<uint64_t>((uint64_t)A.g.vh * (SP == P64 ? 192 : 96), 0xFFFFFFFFull);
+    A.gauge_span = (uint32_t)std::min<uint64_t>((uint64_t)2 * 4 * A.g.vh * link_bytes(SP), 0xFFFFFFFFull);
+    A.in_span = (uint32_t)std::min<uint64_t>((uint64_t)A.g.vh * (SP == P64 ? 192 : SP == P32 ? 96 : 52), 0xFFFFFFFFull);
     const int total = A.nblk_site * A.nslot;
     const int grid = A.swz ? 8 * ((total + 7) / 8) : total;
     hipLaunchKernelGGL((k_dslash<SP, false, EPI_PLAIN, true, false, 1, SRC>), dim3(grid), dim3(BLOCK), 0, s, A);
@@ -1117,21 +1117,32 @@ static void launch_src(DslashArgs A, hipStream_t s)
 
 int launch_dslash_codes(int sp, int src, const DslashArgs &A, hipStream_t s)
 {
-    if (sp != P64 && sp != P32) return -1;
-    if (src == 3) sp == P64 ? launch_src<P64, 3>(A, s) : launch_src<P32, 3>(A, s);
-    else if (src == 2) sp == P64 ? launch_src<P64, 2>(A, s) : launch_src<P32, 2>(A, s);
-    else return -1;
+    if (src == 3) {
+        switch (sp) {
+        case P64: launch_src<P64, 3>(A, s); break;
+        case P32: launch_src<P32, 3>(A, s); break;
+        case P16: launch_src<P16, 3>(A, s); break;
+        case PBF: launch_src<PBF, 3>(A, s); break;
+        default: return -1;
+        }
+    } else if (src == 2 && (sp == P64 || sp == P32)) {
+        sp == P64 ? launch_src<P64, 2>(A, s) : launch_src<P32, 2>(A, s);
+    } else {
+        return -1;
+    }
     return 0;
 }
 
-int launch_dslash_start(int po, const DslashArgs &A, hipStream_t s)
+int launch_dslash_start(int sp, int po, const DslashArgs &A, hipStream_t s)
 {
     if (A.nslot < 1) return 0;
     DslashArgs B = A;
     B.st = nullptr;  // uniform parameters
     bool ok = false;
-    if (po == P16) ok = launch_walk<P32, true, EPI_START, true, 0, P16>(B, s);
-    else if (po == PBF) ok = launch_walk<P32, true, EPI_START, true, 0, PBF>(B, s);
+    if (sp == P32 && po == P16) ok = launch_walk<P32, true, EPI_START, true, 0, P16>(B, s);
+    else if (sp == P32 && po == PBF) ok = launch_walk<P32, true, EPI_START, true, 0, PBF>(B, s);
+    else if (sp == P16 && po == P16) ok = launch_walk<P16, true, EPI_START, true, 0, P16>(B, s);
+    else if (sp == PBF && po == PBF) ok = launch_walk<PBF, true, EPI_START, true, 0, PBF>(B, s);
     return ok ? 0 : -1;
 }
 

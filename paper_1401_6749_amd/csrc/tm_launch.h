@@ -11,14 +11,17 @@ namespace tmk {
 // in the CG update (links of the same precision).  Returns -1 on an
 // unsupported combination.
 int launch_dslash(int sp, bool dag, int epi, bool in2, const DslashArgs &A, hipStream_t s);
-// the last preparation Dslash of an FP32 run with EPI_START: v = Mhat^dag bhat
-// (A.in = A^-dag D'_oe bhat, A.in2 = bhat) written as r (A.r), p (A.out) and
-// x = 0 (A.x) in half precision po (P16 or PBF), with |v|^2 partials; -1 when
-// no timeslice-walk chunk fits the lattice (nothing launched)
-int launch_dslash_start(int po, const DslashArgs &A, hipStream_t s);
+// the last preparation Dslash of a noise run with EPI_START: v = Mhat^dag bhat
+// (A.in = A^-dag D'_oe bhat, A.in2 = bhat, both in precision sp: P32, or the
+// half precision po itself) written as r (A.r), p (A.out) and x = 0 (A.x) in
+// half precision po (P16 or PBF), with |v|^2 partials; -1 when no
+// timeslice-walk chunk fits the lattice or the pair is not built (nothing
+// launched)
+int launch_dslash_start(int sp, int po, const DslashArgs &A, hipStream_t s);
 // plain-epilogue Dslash with Z4-code inputs, uniform (kappa, a):
-//   src 3: hop input A^-1 eta (parity 1 - out_par) and site input eta (prep: bhat = eta + k D A^-1 eta)
-//   src 2: hop input a field, site input eta (reconstruction: A^-1 (eta + k D s))
+//   src 3: hop input A^-1 eta (parity 1 - out_par) and site input eta (prep:
+//          bhat = eta + k D A^-1 eta); output in any storage precision
+//   src 2: hop input a field, site input eta (reconstruction: A^-1 (eta + k D s)); P64 or P32
 int launch_dslash_codes(int sp, int src, const DslashArgs &A, hipStream_t s);
 
 // ---- CG scalars (one block per slot, fixed summation order) ----
