@@ -8,13 +8,26 @@
 
 namespace tmk {
 
-// Fixed-order sum of n doubles by one block of BLOCK threads: thread i sums
-// v[i], v[i+BLOCK], ... sequentially, then the block tree.  Valid in thread 0.
+// Fixed-order sum of n doubles by one block of BLOCK threads: thread i keeps
+// four running sums, of v[i + (4k + j) BLOCK] for j = 0..3, so four loads
+// are in flight per step of its loop; then (s0 + s1) + (s2 + s3) and the
+// block tree.  Valid in thread 0; the same bits for the same n and v.
 __device__ __forceinline__ double sum_fixed(const double *v, int n, double *lds)
 {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += BLOCK) s += v[i];
-    return block_sum<BLOCK>(s, lds);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = threadIdx.x;
+#pragma unroll 2
+    for (; i + 3 * BLOCK < n; i += 4 * BLOCK) {
+        a0 += v[i];
+        a1 += v[i + BLOCK];
+        a2 += v[i + 2 * BLOCK];
+        a3 += v[i + 3 * BLOCK];
+    }
+    // at most three more
+    if (i < n) a0 += v[i];
+    if (i + BLOCK < n) a1 += v[i + BLOCK];
+    if (i + 2 * BLOCK < n) a2 += v[i + 2 * BLOCK];
+    return block_sum<BLOCK>((a0 + a1) + (a2 + a3), lds);
 }
 
 __device__ __forceinline__ bool finite_pos(double v) { return v > 0.0 && v < 1.0e300; }
