@@ -251,8 +251,10 @@ static void load_eta(Batch *b, int slot, Job *j)
     }
 }
 
-// Prep/reconstruction precision of a job: LP noise solves run them in FP32
-// (their target is a 1e-2 residual), everything else in FP64.
+// Prep/reconstruction precision class of a job: P32 for LP noise solves
+// (their target is a 1e-2 residual: reconstruction and contraction in FP32,
+// the preparation in the solve's half precision, see fill_noise_run),
+// P64 for everything else.
 static int prep_prec(const Batch *b, const Job *j)
 {
     return (j->noise && !j->want_true && (b->kind == K_LP16 || b->kind == K_LPBF)) ? P32 : P64;
@@ -341,7 +343,8 @@ static void job_start(Batch *b, int slot, Job *j)
 }
 
 // Noise solves in the n consecutive slots from s0, equal (kappa, a) and
-// preparation precision pp, prepared together:
+// precision class pp (prep_prec), prepared together (FP64 for pp = P64,
+// else in the batch's half precision):
 //   bhat_e = eta_e + kappa D_eo A^-1 eta_o straight from the Z4 codes,
 //   rhs = Mhat^dag bhat = A^dag bhat - kappa^2 D'_eo A^-dag D'_oe bhat,
 // r = p = rhs (rounded to the CG precisions), x = 0.
