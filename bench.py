@@ -999,7 +999,8 @@ def main():
             "lp": (f"{W['half']} storage; Dslash: FP32 arithmetic ("
                    + ("FP32 FMAs with the f16 operands widened inside the instruction"
                       if W["half"] == "f16" else "bf16 widened to FP32")
-                   + "); FP32 vector updates and preparation; truncated at |r|/|r0| = 1e-2"),
+                   + "); FP32 vector updates; right-hand side prepared in the same storage; FP32 "
+                   + "reconstruction and contraction with FP64 sums; truncated at |r|/|r0| = 1e-2"),
             "rhs_per_launch": W["batch"],
             "parallelism": "single GPU, whole lattice resident",
         },
