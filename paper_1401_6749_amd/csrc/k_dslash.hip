@@ -429,6 +429,24 @@ __device__ __forceinline__ void hop_compute_pk(const DslashArgs &A, __amdgpu_buf
     accum<float, MU, S>(acc, w);
 }
 
+// The two transported spin rows of neighbour n of site s (FP64/FP32 storage),
+// before they are added into the output spinor: the projector, the link
+// product and the antiperiodic sign of a temporal hop that wraps.  For the
+// backward t neighbour only s.t is read.
+template <class T, int SP, int MU, bool FWD, bool DAG, class RawT>
+__device__ __forceinline__ void hop_w(const DslashArgs &A, __amdgpu_buffer_rsrc_t gauge, const Site &s, int n,
+                                      const RawT &raw, cpx<T> w[6])
+{
+    constexpr int S = (FWD != DAG) ? -1 : 1;
+    Link<T> L;
+    load_link<SP, T>(gauge, A.g.vh, FWD ? A.out_par : 1 - A.out_par, MU, FWD ? s.cb : n, L);
+    transport<T, MU, S, FWD>(L, raw, w);
+    if (MU == 3 && A.g.tbc < 0 && s.t == (FWD ? A.g.L[3] - 1 : 0)) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) w[k] = cpx<T>{-w[k].re, -w[k].im};
+    }
+}
+
 // One neighbour n of site s from its loaded storage form raw: forward x+mu
 // with (1 - g_mu) U_mu(x), or backward x-mu with (1 + g_mu) U_mu(x-mu)^dagger
 // (projectors swapped for DAG).
@@ -440,16 +458,9 @@ __device__ __forceinline__ void hop_compute(const DslashArgs &A, __amdgpu_buffer
         hop_compute_pk<MU, FWD, DAG>(A, gauge, s, n, raw, acc);
         return;
     }
-    const int vh = A.g.vh;
     constexpr int S = (FWD != DAG) ? -1 : 1;
-    Link<T> L;
-    load_link<SP, T>(gauge, vh, FWD ? A.out_par : 1 - A.out_par, MU, FWD ? s.cb : n, L);
     cpx<T> w[6];
-    transport<T, MU, S, FWD>(L, raw, w);
-    if (MU == 3 && A.g.tbc < 0 && s.t == (FWD ? A.g.L[3] - 1 : 0)) {
-#pragma unroll
-        for (int k = 0; k < 6; k++) w[k] = cpx<T>{-w[k].re, -w[k].im};
-    }
+    hop_w<T, SP, MU, FWD, DAG, RawT>(A, gauge, s, n, raw, w);
     accum<T, MU, S>(acc, w);
 }
 
@@ -703,33 +714,60 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
 // Every input site the walk touches is read from HBM (or L2) once: at each
 // step the thread loads its own site of timeslice t+1, which is at once its
 // forward t neighbour; the block stages that timeslice in LDS for the next
-// step's x, y (and, for small planes, z) neighbours, and the other LDS buffer
-// still holds timeslice t-1, the backward t neighbour.  Only neighbours
-// outside the chunk (the z planes above and below, and y rows at the chunk's
-// edges) are read from global memory, where the blocks working on those
-// chunks have just fetched them into L2.  Two LDS buffers, one barrier per
-// step.  The chunk shape is picked on the host to minimise the halo; each
-// 64-thread wave covers one 64-site reduction tile.  The arithmetic per
-// neighbour is that of k_dslash; the backward t neighbour is summed first.
+// step's x, y (and, for small planes, z) neighbours; the backward t
+// neighbour is the thread's own site of t-1, from a second LDS buffer (half
+// precision) or transported one step early (FP64, FP32: one buffer, see
+// walk_nbuf).  Only neighbours outside the chunk (the z planes above and
+// below, and y rows at the chunk's edges) are read from global memory, where
+// the blocks working on those chunks have just fetched them into L2.  The
+// chunk shape is picked on the host to minimise the halo; each 64-thread
+// wave covers one 64-site reduction tile.  The arithmetic per neighbour is
+// that of k_dslash, in the same order (backward t first, forward t last), so
+// both buffer schemes give the same bits.
 // ---------------------------------------------------------------------------
-constexpr int WSPB = 256;
 #ifndef TM_WALK_MAX_HALF
 #define TM_WALK_MAX_HALF 512
 #endif
-// largest chunk (threads per block) per storage precision, so that the two
-// LDS buffers of two blocks fit a CU: FP64 128 sites (48 KB per block), FP32
-// 256 (48 KB), FP16/BF16 512 (52 KB)
+#ifndef TM_WALK_MAX_F32
+#define TM_WALK_MAX_F32 256
+#endif
+#ifndef TM_WALK_MAX_F64
+#define TM_WALK_MAX_F64 256
+#endif
+// LDS buffers per block: one timeslice or two.  With two, the thread's own
+// site of t+1 goes into the second buffer while the block still reads
+// timeslice t, and the buffer of t-1 serves the backward t neighbour: one
+// barrier per step.  With one (FP64 and FP32, whose sites take 192 and 96
+// bytes), the backward t neighbour of the next step's output is transported
+// while the thread's own site of t is at hand and carried in registers (six
+// complex numbers), the thread's own site of t+1 stays in registers for the
+// forward t neighbour, and the block overwrites the buffer between two
+// barriers: half the LDS per block, so twice the blocks fit a CU.
+#ifndef TM_WALK_NB_F64
+#define TM_WALK_NB_F64 1
+#endif
+#ifndef TM_WALK_NB_F32
+#define TM_WALK_NB_F32 1
+#endif
+template <int SP>
+constexpr int walk_nbuf()
+{
+    return SP == P64 ? TM_WALK_NB_F64 : SP == P32 ? TM_WALK_NB_F32 : 2;
+}
+// largest chunk (threads per block) per storage precision: FP64 256 sites
+// (48 KB, one buffer), FP32 256 (24 KB, one buffer), FP16/BF16 512 (52 KB,
+// two buffers)
 template <int SP>
 constexpr int walk_max()
 {
-    return SP == P64 ? 128 : SP == P32 ? WSPB : TM_WALK_MAX_HALF;
+    return SP == P64 ? TM_WALK_MAX_F64 : SP == P32 ? TM_WALK_MAX_F32 : TM_WALK_MAX_HALF;
 }
 
 template <int SP>
 struct WalkBuf;
 template <>
 struct WalkBuf<P64> {
-    u32x4 q[2][12][128];
+    u32x4 q[walk_nbuf<P64>()][12][walk_max<P64>()];
     __device__ __forceinline__ void get(int b, int d, Raw<P64, double> &r) const
     {
 #pragma unroll
@@ -743,7 +781,7 @@ struct WalkBuf<P64> {
 };
 template <>
 struct WalkBuf<P32> {
-    u32x4 q[2][6][WSPB];
+    u32x4 q[walk_nbuf<P32>()][6][walk_max<P32>()];
     __device__ __forceinline__ void get(int b, int d, Raw<P32, float> &r) const
     {
 #pragma unroll
@@ -896,41 +934,85 @@ __global__ __launch_bounds__(walk_max<SP>(), (walk_waves<SP, EPI>())) void k_dsl
         if (ydir) hy.load(R.in, 0, vh, ydir > 0 ? nbr<1, 1>(g, s1) : nbr<1, -1>(g, s1));
         if (zdir) hz.load(R.in, 0, vh, zdir > 0 ? nbr<2, 1>(g, s1) : nbr<2, -1>(g, s1));
     };
+    constexpr int NB = walk_nbuf<SP>();
+    // the backward t neighbour's projector sign (FWD = false)
+    constexpr int SB = DAG ? -1 : 1;
+    cpx<T> carry[NB == 1 ? 6 : 1];
     {
         RawT r0, r1;
         r0.load(R.in, 0, vh, ((t0 + lt - 1) % lt) * g.st + o);
         r1.load(R.in, 0, vh, t0 * g.st + o);
         if constexpr (PF != 0) halo_load(t0);
-        W.put(1, threadIdx.x, r0);
-        W.put(0, threadIdx.x, r1);
+        if constexpr (NB == 1) {
+            const Site s0 = site_of(g, t0 * g.st + o, A.out_par);
+            hop_w<T, SP, 3, false, DAG, RawT>(A, R.gauge, s0, ((t0 + lt - 1) % lt) * g.st + o, r0, carry);
+            W.put(0, threadIdx.x, r1);
+        } else {
+            W.put(1, threadIdx.x, r0);
+            W.put(0, threadIdx.x, r1);
+        }
     }
     __syncthreads();
     for (int k = 0; k < tw; k++) {
         const int t = t0 + k;
         const int cb = t * g.st + o;
         RawT nxt;
-        nxt.load(R.in, 0, vh, ((t + 1) % lt) * g.st + o);
-        const WalkPos w{k & 1, yy, zz};
+        if constexpr (NB != 1) nxt.load(R.in, 0, vh, ((t + 1) % lt) * g.st + o);
+        const WalkPos w{NB == 1 ? 0 : (k & 1), yy, zz};
         const Site s = site_of(g, cb, A.out_par);
         cpx<T> acc[12];
 #pragma unroll
         for (int q = 0; q < 12; q++) acc[q] = cpx<T>{(T)0, (T)0};
-        // backward t neighbour first: it frees this thread's slot of timeslice
-        // t-1, which then takes timeslice t+1 (the forward t neighbour now and
-        // the next step's spatial neighbours), so nxt is not held in registers
-        // through the other seven neighbours.
-        walk_dir<SP, 3, false, DAG>(A, R, s, W, w, acc, hy, hz, pf);
-        W.put(w.buf ^ 1, threadIdx.x, nxt);
+        if constexpr (NB == 1) {
+            // the neighbours in the same order as with two buffers: backward
+            // t (carried), x, y, z, forward t (nxt, still in registers)
+            accum<T, 3, SB>(acc, carry);
 #pragma unroll 1
-        for (int d = 0; d < 7; d++) {
-            switch (__builtin_amdgcn_readfirstlane(d)) {
-            case 0: walk_dir<SP, 0, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
-            case 1: walk_dir<SP, 0, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
-            case 2: walk_dir<SP, 1, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
-            case 3: walk_dir<SP, 1, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
-            case 4: walk_dir<SP, 2, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
-            case 5: walk_dir<SP, 2, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
-            default: walk_dir<SP, 3, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+            for (int d = 0; d < 6; d++) {
+                switch (__builtin_amdgcn_readfirstlane(d)) {
+                case 0: walk_dir<SP, 0, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                case 1: walk_dir<SP, 0, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                case 2: walk_dir<SP, 1, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                case 3: walk_dir<SP, 1, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                case 4: walk_dir<SP, 2, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                default: walk_dir<SP, 2, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                }
+            }
+            // the thread's own site of t+1, loaded only now so that it is not
+            // held in registers through the spatial neighbours
+            nxt.load(R.in, 0, vh, ((t + 1) % lt) * g.st + o);
+            hop_compute<T, SP, 3, true, DAG, RawT>(A, R.gauge, s, nbr<3, 1>(g, s), nxt, acc);
+            if (k + 1 < tw) {
+                __syncthreads();  // every read of timeslice t is done
+                // only this thread writes its slot: its own site of t (the
+                // next output's backward t neighbour, input index cb) is read
+                // back, then replaced by its site of t+1; the backward hop
+                // reads only the output's t
+                RawT own;
+                W.get(0, threadIdx.x, own);
+                W.put(0, threadIdx.x, nxt);
+                Site s1 = s;
+                s1.t = t + 1 == lt ? 0 : t + 1;
+                hop_w<T, SP, 3, false, DAG, RawT>(A, R.gauge, s1, cb, own, carry);
+            }
+        } else {
+            // backward t neighbour first: it frees this thread's slot of
+            // timeslice t-1, which then takes timeslice t+1 (the forward t
+            // neighbour now and the next step's spatial neighbours), so nxt is
+            // not held in registers through the other seven neighbours.
+            walk_dir<SP, 3, false, DAG>(A, R, s, W, w, acc, hy, hz, pf);
+            W.put(w.buf ^ 1, threadIdx.x, nxt);
+#pragma unroll 1
+            for (int d = 0; d < 7; d++) {
+                switch (__builtin_amdgcn_readfirstlane(d)) {
+                case 0: walk_dir<SP, 0, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                case 1: walk_dir<SP, 0, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                case 2: walk_dir<SP, 1, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                case 3: walk_dir<SP, 1, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                case 4: walk_dir<SP, 2, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                case 5: walk_dir<SP, 2, false, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                default: walk_dir<SP, 3, true, DAG>(A, R, s, W, w, acc, hy, hz, pf); break;
+                }
             }
         }
         // next timeslice's halo, while its owners are reading it
