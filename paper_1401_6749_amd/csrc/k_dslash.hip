@@ -829,8 +829,9 @@ struct WalkPos {
 #define TM_WALK_HALO_PF 0
 #endif
 
-// t neighbours: this thread's own site in timeslices t+-1, both in the
-// other LDS buffer (t-1 until the backward neighbour is done, t+1 after).
+// t neighbours (two-buffer walk only): this thread's own site in timeslices
+// t+-1, both in the other LDS buffer (t-1 until the backward neighbour is
+// done, t+1 after).
 // y/z neighbours outside the chunk come from the prefetched halo (hy, hz)
 // when there is one, else from global memory.
 template <int SP, int MU, bool FWD, bool DAG, class RawT>

@@ -78,6 +78,15 @@ def test_traffic_from_scales_by_the_copy(tmp_path, monkeypatch):
     assert d["kernel_hash"] == bench.kernel_hash() and d["dispatches"] == [3, 1]
 
 
+def test_kernel_hash_ignores_comments_only():
+    src = 'int f(int x) { // twice\n  return 2 * x;  /* doubled */ }\nconst char *s = "// kept";\n'
+    same = 'int f(int x)\n{\n    return 2 * x;\n}\n// a note\nconst char *s = "// kept";'
+    assert bench.code_text(src) == bench.code_text(same)
+    assert bench.code_text(src) != bench.code_text(src.replace("2 * x", "3 * x"))
+    assert bench.code_text(src) != bench.code_text(src.replace('"// kept"', '"// gone"'))
+    assert len(bench.kernel_hash()) == 16
+
+
 def test_trace_summary_table(tmp_path):
     (tmp_path / "b_kernel_stats.csv").write_text(
         "Name,Calls,TotalDurationNs,AverageNs,Percentage,MinNs,MaxNs,StdDev\n"
