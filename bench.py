@@ -218,6 +218,37 @@ def contract_rates(torch, tm, inputs, ctx, g, W):
     return out
 
 
+def update_rates(torch, tm, inputs, ctx, g, W):
+    """The CG direction update (x += alpha p, then p = r + beta p) alone
+    through tm_cg_update, on even-half fields at the solver's slot pitch, in
+    the precisions the solves store them in (FP16 LP, FP32 HP inner, FP64
+    plain), timed with HIP events on its stream; algorithmic bytes = p, r, x
+    read and x, p written, 5 spinors per site and right-hand side."""
+    dims = W["dims"]
+    vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    out = []
+    for prec, n in ((W["half"], W["batch"]), ("f32", W["batch"]), ("f64", W["batch"]), ("f64", 1)):
+        fb = tm.tm_field_bytes(g, prec, True)
+        hb = fb // 2
+        pitch = slot_pitch(hb)
+        tmp = torch.empty(fb, dtype=torch.uint8, device="cuda")
+        fields = []
+        for k in range(3):  # p, r, x: the even half of a random field in every slot
+            tm.tm_field_import(ctx, g, prec, 1, tm.canonical_to_torch(inputs.random_spinor(dims, 40 + k)[None]), tmp)
+            f = torch.empty(n * pitch, dtype=torch.uint8, device="cuda")
+            for r in range(n):
+                f[r * pitch:r * pitch + hb].copy_(tmp[:hb])
+            fields.append(f)
+        p, r, x = fields
+        alpha, beta = [0.01] * n, [0.5] * n
+        t = event_time(torch, lambda: tm.tm_cg_update(ctx, g, prec, n, p, r, x, pitch, alpha, beta), 20)
+        alg = vh * n * 5 * SPINOR_BYTES[prec]
+        out.append({"prec": prec, "nrhs": n, "launch_us": round(t * 1e6, 1), "alg_bytes": alg,
+                    "alg_GBs": round(alg / t / 1e9, 1), "frac_8TBs": round(alg / t / 1e9 / HBM_PEAK_GBS, 4)})
+        del p, r, x, fields, tmp
+    return out
+
+
 def plain_segment(tm, np, ctx, g, W, n_src, t_step, tsm_var, batches=(1, 12)):
     """Plain FP64 CG (Sec. 2, Eq. estiM: no TSM, FP64 to 1e-10) on the same
     GPU, one and 12 right-hand sides per launch: sources/s of each, and the
@@ -928,10 +959,13 @@ def main():
             f"{plain['tsm_effective_speedup_deriv_median']:.1f}x")
 
     roofline = measure_roofline(torch, tm, inputs, ctx, g, W, args.workload)
-    rates = crates = None
+    rates = crates = urates = None
     if not args.no_extra:
         rates = kernel_rates(torch, tm, inputs, ctx, g, W)
         log("hop rates: " + ", ".join(f"{r['prec']}x{r['nrhs']} {r['launch_us']}us {r['alg_GBs']}GB/s" for r in rates))
+        urates = update_rates(torch, tm, inputs, ctx, g, W)
+        log("update rates: " + ", ".join(f"{r['prec']}x{r['nrhs']} {r['launch_us']}us {r['alg_GBs']}GB/s"
+                                         for r in urates))
         crates = contract_rates(torch, tm, inputs, ctx, g, W)
         log("contraction: " + ", ".join(f"{r['prec']}x{r['sources']} {r['call_us']}us {r['alg_GBs']}GB/s"
                                         for r in crates))
@@ -1042,6 +1076,7 @@ def main():
         "roofline": roofline,
         "kernel_rates": rates,
         "contraction_rates": crates,
+        "update_rates": urates,
         "bf16_lp": bf16,
         "configs": configs,
         "cpu_baseline": cpu,

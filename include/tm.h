@@ -235,6 +235,27 @@ int tm_cg_solve(tm_context *ctx, const tm_gauge *gauge, double kappa, double two
                 const tm_solver_params *params, int nrhs, const double *b, double *x,
                 tm_solve_stats *stats, void *hip_stream);
 
+/* The direction update that ends every CG iteration (Sec. 2.1, the CG
+ * solver), as tm_cg_solve and tm_loops_tsm apply it, on nrhs caller fields:
+ *   x_i += alpha_i p_i   (skipped when x is NULL), then
+ *   p_i  = r_i + beta_i p_i,
+ * both from the old p_i, with the solver's kernel: arithmetic in FP64 for
+ * TM_PREC_F64, in FP32 for the other precisions, each result rounded to
+ * the storage format of prec.
+ *   p, r, x      device, nrhs even-half fields in the layout of prec
+ *                (tm_field_bytes(gauge, prec, 1) bytes each), field i at
+ *                base + i * stride; 16-byte aligned; p overlaps neither
+ *                r nor x, r and x do not overlap
+ *   stride       bytes between consecutive fields: a multiple of 16, at
+ *                least one field
+ *   alpha, beta  host, nrhs finite doubles each (copied at the call)
+ *   nrhs         1..16
+ * The gauge field only fixes the lattice; its links are not read.
+ * Asynchronous on hip_stream; allocates nothing.  Errors: TM_ERR_ARG,
+ * TM_ERR_HIP. */
+int tm_cg_update(tm_context *ctx, const tm_gauge *gauge, tm_prec prec, int nrhs, void *p, const void *r, void *x,
+                 size_t stride, const double *alpha, const double *beta, void *hip_stream);
+
 /* ------------------------------------------------------------------ */
 /* Noise (Sec. 2: Z_N noise with Eq. 1-2; Z4 here)                      */
 /* ------------------------------------------------------------------ */

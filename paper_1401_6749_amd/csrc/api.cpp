@@ -602,6 +602,36 @@ static void job_from(Job &j, const tm_solver_params &p, double kappa, double a)
     j.delta = p.delta > 0 ? p.delta : TM_DEFAULT_DELTA;
 }
 
+extern "C" int tm_cg_update(tm_context *ctx, const tm_gauge *G, tm_prec prec, int nrhs, void *p, const void *r,
+                            void *x, size_t stride, const double *alpha, const double *beta, void *hip_stream)
+{
+    if (!ctx) return TM_ERR_ARG;
+    const int pi = prec_index(prec);
+    if (!G || pi < 0) return set_err(ctx, TM_ERR_ARG, "tm_cg_update: bad gauge or precision");
+    if (nrhs < 1 || nrhs > MAX_SLOTS) return set_err(ctx, TM_ERR_ARG, "tm_cg_update: nrhs must be 1..%d", MAX_SLOTS);
+    if (!p || !r || !alpha || !beta) return set_err(ctx, TM_ERR_ARG, "tm_cg_update: null argument");
+    const size_t hb = half_bytes(pi, G->g);
+    const bool aligned = (uintptr_t)p % 16 == 0 && (uintptr_t)r % 16 == 0 && (uintptr_t)x % 16 == 0;
+    if (stride < hb || stride % 16 || !aligned)
+        return set_err(ctx, TM_ERR_ARG, "tm_cg_update: fields must be 16-byte aligned, the stride a multiple of 16 "
+                                        "and at least one field");
+    const size_t span = stride * (size_t)(nrhs - 1) + hb;
+    if (overlap(p, span, r, span) || (x && (overlap(p, span, x, span) || overlap(r, span, x, span))))
+        return set_err(ctx, TM_ERR_ARG, "tm_cg_update: p, r and x must not overlap");
+    UpdateCoefs c;
+    std::memset(&c, 0, sizeof(c));
+    for (int i = 0; i < nrhs; i++) {
+        if (!std::isfinite(alpha[i]) || !std::isfinite(beta[i]))
+            return set_err(ctx, TM_ERR_ARG, "tm_cg_update: alpha and beta must be finite");
+        c.alpha[i] = alpha[i];
+        c.beta[i] = beta[i];
+    }
+    launch_p_update_coefs(pi, G->g, (char *)p, (const char *)r, (char *)x, stride, c, nrhs, ctx->swz,
+                          (hipStream_t)hip_stream);
+    TM_HIP(ctx, hipGetLastError());
+    return TM_OK;
+}
+
 extern "C" int tm_cg_solve(tm_context *ctx, const tm_gauge *G, double kappa, double a, const tm_solver_params *params,
                            int nrhs, const double *b, double *x, tm_solve_stats *stats, void *hip_stream)
 {

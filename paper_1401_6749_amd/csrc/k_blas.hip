@@ -190,18 +190,38 @@ void launch_reduce(const double *partial, int nblk, int n, double *out, hipStrea
 // ---------------------------------------------------------------------------
 // End of a CG iteration per slot: x += alpha p if the iteration took a step
 // (x != nullptr and the slot's step is owed), then p = r + beta p if the slot
-// keeps running.  Both read the old p.
-template <int SP, int XR>
+// keeps running.  Both read the old p.  The coefficients come from the
+// slot's device state (the solver) or, for a standalone update, from the
+// kernel's arguments.
+struct UpdCoef {
+    bool step, run;
+    double alpha, beta;
+};
+struct SlotCoef {
+    const SlotState *st;
+    __device__ __forceinline__ UpdCoef operator()(int slot, bool has_x) const
+    {
+        const SlotState &S = st[slot];
+        return {has_x && S.xpend != 0, S.status == ST_RUNNING, S.alpha, S.beta};
+    }
+};
+struct ArgCoef {
+    UpdateCoefs c;
+    __device__ __forceinline__ UpdCoef operator()(int slot, bool has_x) const
+    {
+        return {has_x, true, c.alpha[slot], c.beta[slot]};
+    }
+};
+template <int SP, int XR, class Coef>
 __global__ __launch_bounds__(BLOCK) void k_p_update(Geom g, char *p, size_t p_slot, const char *r, size_t r_slot,
-                                                    char *x, size_t x_slot, SlotState *st, int nslot, int nblk,
+                                                    char *x, size_t x_slot, Coef coef, int nslot, int nblk,
                                                     int swz)
 {
     using T = typename Real<SP>::T;
     int sblk, slot;
     if (!map_block(nblk, nslot, swz, sblk, slot)) return;
-    const SlotState &S = st[slot];
-    const bool step = x != nullptr && S.xpend != 0;
-    const bool run = S.status == ST_RUNNING;
+    const UpdCoef S = coef(slot, x != nullptr);
+    const bool step = S.step, run = S.run;
     if (!step && !run) return;
     const int cb = sblk * BLOCK + threadIdx.x;
     if (cb >= g.vh) return;
@@ -227,23 +247,36 @@ __global__ __launch_bounds__(BLOCK) void k_p_update(Geom g, char *p, size_t p_sl
     }
 }
 
-void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot, char *x,
-                     size_t x_slot, SlotState *st, int nslot, int swz, hipStream_t s)
+template <class Coef>
+static void launch_p_update_t(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot,
+                              char *x, size_t x_slot, const Coef &coef, int nslot, int swz, hipStream_t s)
 {
     const int nblk = nblk_of(g);
     const int total = nblk * nslot;
     const int grid = swz ? 8 * ((total + 7) / 8) : total;
-#define TMK_P(SP, XR)                                                                                   \
-    if (sp == SP && xr == XR) {                                                                        \
-        hipLaunchKernelGGL((k_p_update<SP, XR>), dim3(grid), dim3(BLOCK), 0, s, g, p, p_slot, r, r_slot, \
-                           x, x_slot, st, nslot, nblk, swz);                                            \
-        return;                                                                                         \
+#define TMK_P(SP, XR)                                                                                         \
+    if (sp == SP && xr == XR) {                                                                              \
+        hipLaunchKernelGGL((k_p_update<SP, XR, Coef>), dim3(grid), dim3(BLOCK), 0, s, g, p, p_slot, r, r_slot, \
+                           x, x_slot, coef, nslot, nblk, swz);                                                \
+        return;                                                                                               \
     }
     TMK_P(P64, P64)
     TMK_P(P32, P32)
     TMK_P(P16, P16)
     TMK_P(PBF, PBF)
 #undef TMK_P
+}
+
+void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot, char *x,
+                     size_t x_slot, SlotState *st, int nslot, int swz, hipStream_t s)
+{
+    launch_p_update_t(sp, xr, g, p, p_slot, r, r_slot, x, x_slot, SlotCoef{st}, nslot, swz, s);
+}
+
+void launch_p_update_coefs(int sp, const Geom &g, char *p, const char *r, char *x, size_t slot_bytes,
+                           const UpdateCoefs &c, int nslot, int swz, hipStream_t s)
+{
+    launch_p_update_t(sp, sp, g, p, slot_bytes, r, slot_bytes, x, slot_bytes, ArgCoef{c}, nslot, swz, s);
 }
 
 // ---------------------------------------------------------------------------

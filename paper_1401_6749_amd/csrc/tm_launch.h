@@ -32,6 +32,14 @@ void launch_cg_beta(SlotState *st, const double *partial, int nslot, int nblk, h
 // running slots (sp = p precision, xr = x and r precision)
 void launch_p_update(int sp, int xr, const Geom &g, char *p, size_t p_slot, const char *r, size_t r_slot, char *x,
                      size_t x_slot, SlotState *st, int nslot, int swz, hipStream_t s);
+// the same update with per-slot coefficients given by value (every slot
+// steps x if x is not null and updates p); fields of one precision sp,
+// slot i at base + i * slot_bytes
+struct UpdateCoefs {
+    double alpha[MAX_SLOTS], beta[MAX_SLOTS];
+};
+void launch_p_update_coefs(int sp, const Geom &g, char *p, const char *r, char *x, size_t slot_bytes,
+                           const UpdateCoefs &c, int nslot, int swz, hipStream_t s);
 // start n consecutive slots: rr0 = sum of the slot's nblk partials, status
 // RUNNING (or CONVERGED if rr0 == 0); parameters per slot
 struct SlotStartParams {

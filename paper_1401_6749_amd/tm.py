@@ -122,6 +122,8 @@ _sig = {
                                   c_void_p, c_size_t, c_void_p]),
     "tm_cg_solve": (c_int, [c_void_p, c_void_p, c_double, c_double, ctypes.POINTER(tm_solver_params), c_int,
                             c_void_p, c_void_p, ctypes.POINTER(tm_solve_stats), c_void_p]),
+    "tm_cg_update": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p,
+                             c_void_p, c_void_p]),
     "tm_z4_source": (c_int, [c_void_p, ctypes.POINTER(c_int), c_uint64, c_uint64, c_void_p, c_void_p]),
     "tm_loops_tsm": (c_int, [c_void_p, c_void_p, ctypes.POINTER(tm_tsm_params), c_void_p, c_void_p, c_void_p,
                              c_void_p, ctypes.POINTER(tm_tsm_stats)]),
@@ -299,6 +301,19 @@ def tm_dslash_noalloc(ctx, gauge, op, kappa, two_kappa_mu, prec, nrhs, inp, in_s
 def solver_params(mode="f64", tol=1e-10, max_iter=100000, fixed_iters=0, half="f16", delta=1e-3, chunk=0):
     return tm_solver_params(MODES[mode], PREC[half], float(tol), int(max_iter), int(fixed_iters), float(delta),
                             int(chunk))
+
+
+def tm_cg_update(ctx, gauge, prec, nrhs, p, r, x, stride, alpha, beta, stream=None, check=True):
+    """CG direction update on nrhs even-half fields (device, layout of prec):
+    x += alpha p (x may be None), then p = r + beta p."""
+    al = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64).reshape(-1))
+    be = np.ascontiguousarray(np.asarray(beta, dtype=np.float64).reshape(-1))
+    assert al.size == nrhs and be.size == nrhs
+    rc = _lib.tm_cg_update(ctx, gauge, PREC[prec], int(nrhs), _ptr(p), _ptr(r), _ptr(x), int(stride),
+                           al.ctypes.data, be.ctypes.data, _stream(stream))
+    if check:
+        _check(ctx, rc, "tm_cg_update")
+    return rc
 
 
 def tm_cg_solve(ctx, gauge, kappa, two_kappa_mu, params, nrhs, b, x, stream=None, check=True):
