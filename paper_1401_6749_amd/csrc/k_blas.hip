@@ -227,23 +227,25 @@ __global__ __launch_bounds__(BLOCK) void k_p_update(Geom g, char *p, size_t p_sl
     if (cb >= g.vh) return;
     cpx<T> pv[12];
     char *ps = p + (size_t)slot * p_slot;
+    char *xs = step ? x + (size_t)slot * x_slot : nullptr;
     SpinorIO<SP>::load(ps, g.vh, cb, pv);
+    // x and p are written with non-temporal stores: each is next read by a
+    // later kernel, after far more data than the caches hold has passed
     if (step) {
         cpx<T> xv[12];
-        char *xs = x + (size_t)slot * x_slot;
         SpinorIO<XR>::load(xs, g.vh, cb, xv);
         const T al = (T)S.alpha;
 #pragma unroll
         for (int k = 0; k < 12; k++) xv[k] = xv[k] + cscale(al, pv[k]);
-        SpinorIO<XR>::store(xs, g.vh, cb, xv);
+        SpinorIO<XR>::template store<T, true>(xs, g.vh, cb, xv);
     }
     if (run) {
         cpx<T> rv[12];
-        const T beta = (T)S.beta;
         SpinorIO<XR>::load(r + (size_t)slot * r_slot, g.vh, cb, rv);
+        const T beta = (T)S.beta;
 #pragma unroll
         for (int k = 0; k < 12; k++) pv[k] = rv[k] + cscale(beta, pv[k]);
-        SpinorIO<SP>::store(ps, g.vh, cb, pv);
+        SpinorIO<SP>::template store<T, true>(ps, g.vh, cb, pv);
     }
 }
 
