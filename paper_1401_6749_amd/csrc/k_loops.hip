@@ -90,9 +90,11 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 // ---------------------------------------------------------------------------
 // Contractions.  A block owns a chunk of CPB sites of one timeslice (sites
 // of parity 0, then parity 1, each in cb order) for one source.  For FP32
-// solutions it has one wave per kind of spin matrix: the nine waves walk the
-// same sites at the same time, so the solution, the links and the codes of a
-// site come from HBM once and the other kinds hit the caches.  Each lane
+// solutions each kind of spin matrix has a one-wave block of its own (the
+// nine blocks of a chunk and source are consecutive, so they run together on
+// one XCD and the other kinds find a site's solution, links and codes in its
+// L2); single-wave blocks fill the four SIMDs of a CU evenly and fit beside
+// the Dslash blocks of a concurrent stream.  Each lane
 // accumulates its sites, the wave reduces in a fixed order and writes one
 // partial per (timeslice, chunk, kind); a second kernel sums the chunks of
 // each timeslice in order and applies one complex factor.
@@ -103,8 +105,7 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 // 2^-1/2), or, for the one-end trick, a field: the solution itself (factor
 // -2ia, isovector) with s the solution or D_W applied to it (factor 2).
 // ---------------------------------------------------------------------------
-// waves per SIMD the register allocation must allow: a block of nine waves
-// needs three on one SIMD
+// waves per SIMD the register allocation of the FP32 kinds must allow
 #ifndef TM_CONTRACT_WAVES
 #define TM_CONTRACT_WAVES 3
 #endif
@@ -306,30 +307,47 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
     }
 }
 
-// Waves per contraction block: one per kind for FP32 solutions; FP64 ones
-// (registers for FP64 products) take one wave that computes the kinds in turn.
+// Waves per contraction block: for FP32 solutions one per kind, with
+// TM_CONTRACT_KPB kinds per block (the 9 kinds in 9 / KPB blocks; measured at
+// 32^3x64, 12 sources: 9 kinds per block 3.70 ms, 3 kinds 3.25 ms, 1 kind
+// 3.20 ms, same bits); FP64 ones (registers for FP64 products) take one wave
+// that computes the kinds in turn.
+#ifndef TM_CONTRACT_KPB
+#define TM_CONTRACT_KPB 1
+#endif
+static_assert(9 % TM_CONTRACT_KPB == 0, "kinds per block must divide 9");
 template <int SPS, int NK>
 constexpr int contract_waves()
 {
-    return SPS == P32 ? NK : 1;
+    return SPS == P32 ? (NK == 9 ? TM_CONTRACT_KPB : NK) : 1;
+}
+// blocks per source and site chunk
+template <int SPS, int NK>
+constexpr int contract_groups()
+{
+    return SPS == P32 && NK == 9 ? 9 / TM_CONTRACT_KPB : 1;
 }
 
 // partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
-// Logical block l handles source i = l mod n of site chunk l / n: the n
+// Logical block lb handles kind group lb mod NG of logical unit l = lb / NG,
+// and l source i = l mod n of site chunk l / n: the n
 // sources of a chunk run back to back on one XCD (the hardware hands block b
-// to XCD b mod 8, so l = (b mod 8) * per + b / 8 gives each XCD a contiguous
+// to XCD b mod 8, so lb = (b mod 8) * per + b / 8 gives each XCD a contiguous
 // range of logical blocks) and share the chunk's links in its L2.  The left
 // vector is the source's codes (FIELD false) or the field pair
 // (l_even, l_odd) + i * l_stride; NK = 9 (all kinds) or 1 (local only).
 template <int SPS, bool FIELD, int NK>
-__global__ __launch_bounds__((64 * contract_waves<SPS, NK>()), (contract_waves<SPS, NK>() > 1 ? TM_CONTRACT_WAVES : 1))
+__global__ __launch_bounds__((64 * contract_waves<SPS, NK>()),
+                             (SPS == P32 && NK == 9 ? TM_CONTRACT_WAVES : 1))
 void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd, size_t s_stride, const char *l_even,
                 const char *l_odd, size_t l_stride, const uint32_t *codes, double *cpart, int nchunk,
                 size_t part_stride, int n, int total)
 {
+    constexpr int NG = contract_groups<SPS, NK>();
     const int per = (total + 7) >> 3;
-    const int l = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
-    if (l >= total) return;  // uniform over the block
+    const int lb = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+    if (lb >= total) return;  // uniform over the block
+    const int kg = lb % NG, l = lb / NG;
     const int i = l % n, tc = l / n;
     const int t = tc / nchunk, chunk = tc - t * nchunk;
     const char *s_fld[2] = {s_even + (size_t)i * s_stride, s_odd + (size_t)i * s_stride};
@@ -344,7 +362,7 @@ void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd, si
     wave_write32(acc, dst + (K) * 32);
     if constexpr (NK == 1) {
         TMK_KIND(0)
-    } else if constexpr (contract_waves<SPS, NK>() == 1) {
+    } else if constexpr (contract_waves<SPS, NK>() == 1 && NG == 1) {
         TMK_KIND(0)
         TMK_KIND(1)
         TMK_KIND(2)
@@ -355,8 +373,8 @@ void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd, si
         TMK_KIND(7)
         TMK_KIND(8)
     } else {
-        // wave w computes kind w
-        switch (__builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6)) {
+        // wave w of group kg computes kind kg * waves + w
+        switch (__builtin_amdgcn_readfirstlane(kg * contract_waves<SPS, NK>() + ((int)threadIdx.x >> 6))) {
         case 0: TMK_KIND(0) break;
         case 1: TMK_KIND(1) break;
         case 2: TMK_KIND(2) break;
@@ -403,7 +421,7 @@ static void contract_t(int sps, const Geom &g, const void *gauge, const char *s_
     const int nchunk = contract_nchunk(g);
     const int lt = g.L[3];
     const size_t ps = contract_part_doubles(g);
-    const int total = lt * nchunk * n;
+    const int total = lt * nchunk * n * (sps == P32 ? contract_groups<P32, NK>() : 1);
     const unsigned nb = (unsigned)(8 * ((total + 7) / 8));
     if (sps == P32)
         hipLaunchKernelGGL((k_contract<P32, FIELD, NK>), dim3(nb), dim3(64 * contract_waves<P32, NK>()), 0, s, g,
