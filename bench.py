@@ -400,8 +400,9 @@ def counter_summary(out_json: str, kernel: str, bench_args: str, dbs, sites: int
     and WRITE_SIZE turned into bytes by what the same counters read for the
     1 GiB streaming copy in the same run, and, where the counters are there,
     the VALU issue share (a wave64 VALU instruction takes four cycles of one
-    of the 1024 SIMDs; GRBM_GUI_ACTIVE sums the cycles of the 8 XCDs) and the
-    VALU lane instructions per site and source."""
+    of the 1024 SIMDs; GRBM_GUI_ACTIVE sums the cycles of the 8 XCDs), the
+    time those instructions take to issue at 2.4 GHz, and the VALU lane
+    instructions per site and source."""
     import sqlite3
 
     means, copy, commands, n = {}, {}, [], {}
@@ -430,11 +431,16 @@ def counter_summary(out_json: str, kernel: str, bench_args: str, dbs, sites: int
     if "WRITE_SIZE" in means and "WRITE_SIZE" in copy:
         d["write_scale"] = round((1 << 30) / (copy["WRITE_SIZE"] * 1024.0), 4)
         d["write_bytes_per_dispatch"] = round(means["WRITE_SIZE"] * 1024.0 * d["write_scale"])
+    if "SQ_INSTS_VALU" in means:
+        # the time the counted instructions take to issue at 2.4 GHz, to set
+        # beside the kernel's traced duration (GRBM_GUI_ACTIVE can undercount
+        # a kernel's span, so its share below may exceed 1)
+        d["valu_issue_floor_us_at_2400MHz"] = round(means["SQ_INSTS_VALU"] * 4.0 / (1024.0 * 2400.0), 1)
+        d["valu_lane_instructions_per_site_source"] = round(means["SQ_INSTS_VALU"] * 64.0 / (sites * sources), 1)
     if "SQ_INSTS_VALU" in means and "GRBM_GUI_ACTIVE" in means:
         cyc = means["GRBM_GUI_ACTIVE"] / 8.0
         d["gpu_cycles_per_xcd"] = round(cyc)
         d["valu_issue_busy"] = round(means["SQ_INSTS_VALU"] * 4.0 / (1024.0 * cyc), 3)
-        d["valu_lane_instructions_per_site_source"] = round(means["SQ_INSTS_VALU"] * 64.0 / (sites * sources), 1)
     if "TCC_HIT_sum" in means and "TCC_MISS_sum" in means:
         d["l2_hit_rate"] = round(means["TCC_HIT_sum"] / (means["TCC_HIT_sum"] + means["TCC_MISS_sum"]), 3)
     out["sites_per_dispatch"] = sites

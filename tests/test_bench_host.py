@@ -52,6 +52,8 @@ def test_counter_summary_calibration_and_issue_share(tmp_path):
     assert d["derived"]["valu_issue_busy"] == pytest.approx(0.5, abs=1e-3)
     assert d["derived"]["valu_lane_instructions_per_site_source"] == pytest.approx(3.072e8 * 64 / 12000, rel=1e-6)
     assert d["derived"]["l2_hit_rate"] == pytest.approx(0.75)
+    # 3.072e8 wave instructions over 1024 SIMDs at four cycles each and 2.4 GHz
+    assert d["derived"]["valu_issue_floor_us_at_2400MHz"] == pytest.approx(3.072e8 * 4 / 1024 / 2400, abs=0.1)
     # the hop's row is not mixed in, and every command names committed files only
     assert d["per_dispatch_means"]["SQ_INSTS_VALU"] == pytest.approx(3.072e8)
     assert all("_work" not in c for c in d["commands"])
