@@ -89,12 +89,12 @@ void launch_z4_canonical(const Geom &g, uint64_t seed, uint64_t src, double *out
 
 // ---------------------------------------------------------------------------
 // Contractions.  A block owns a chunk of CPB sites of one timeslice (sites
-// of parity 0, then parity 1, each in cb order) for one source.  For FP32
-// solutions each kind of spin matrix has a one-wave block of its own (the
-// nine blocks of a chunk and source are consecutive, so they run together on
-// one XCD and the other kinds find a site's solution, links and codes in its
-// L2); single-wave blocks fill the four SIMDs of a CU evenly and fit beside
-// the Dslash blocks of a concurrent stream.  Each lane
+// of parity 0, then parity 1, each in cb order) for one source.  Each kind
+// of spin matrix has a one-wave block of its own (the nine blocks of a chunk
+// and source are consecutive, so they run together on one XCD and the other
+// kinds find a site's solution, links and codes in its L2); single-wave
+// blocks fill the four SIMDs of a CU evenly and fit beside the Dslash blocks
+// of a concurrent stream.  Each lane
 // accumulates its sites, the wave reduces in a fixed order and writes one
 // partial per (timeslice, chunk, kind); a second kernel sums the chunks of
 // each timeslice in order and applies one complex factor.
@@ -307,11 +307,11 @@ __device__ __forceinline__ void contract_kind(const Geom &g, const void *G, cons
     }
 }
 
-// Waves per contraction block: for FP32 solutions one per kind, with
-// TM_CONTRACT_KPB kinds per block (the 9 kinds in 9 / KPB blocks; measured at
-// 32^3x64, 12 sources: 9 kinds per block 3.70 ms, 3 kinds 3.25 ms, 1 kind
-// 3.20 ms, same bits); FP64 ones (registers for FP64 products) take one wave
-// that computes the kinds in turn.
+// Contraction blocks: FP32 solutions take TM_CONTRACT_KPB kinds per block,
+// one wave per kind (the 9 kinds in 9 / KPB blocks; measured at 32^3x64, 12
+// sources: 9 kinds per block 3.70 ms, 3 kinds 3.25 ms, 1 kind 3.20 ms, same
+// bits); FP64 ones one kind per single-wave block (before, one wave computed
+// the nine kinds in turn: 0.99 ms per source against 0.51 ms).
 #ifndef TM_CONTRACT_KPB
 #define TM_CONTRACT_KPB 1
 #endif
@@ -319,13 +319,13 @@ static_assert(9 % TM_CONTRACT_KPB == 0, "kinds per block must divide 9");
 template <int SPS, int NK>
 constexpr int contract_waves()
 {
-    return SPS == P32 ? (NK == 9 ? TM_CONTRACT_KPB : NK) : 1;
+    return SPS == P32 && NK == 9 ? TM_CONTRACT_KPB : 1;
 }
 // blocks per source and site chunk
 template <int SPS, int NK>
 constexpr int contract_groups()
 {
-    return SPS == P32 && NK == 9 ? 9 / TM_CONTRACT_KPB : 1;
+    return NK == 9 ? 9 / contract_waves<SPS, NK>() : 1;
 }
 
 // partial layout: cpart[(t * nchunk + chunk) * 288 + kind * 32 + ab * 2 + re/im]
@@ -337,8 +337,7 @@ constexpr int contract_groups()
 // vector is the source's codes (FIELD false) or the field pair
 // (l_even, l_odd) + i * l_stride; NK = 9 (all kinds) or 1 (local only).
 template <int SPS, bool FIELD, int NK>
-__global__ __launch_bounds__((64 * contract_waves<SPS, NK>()),
-                             (SPS == P32 && NK == 9 ? TM_CONTRACT_WAVES : 1))
+__global__ __launch_bounds__((64 * contract_waves<SPS, NK>()), (SPS == P32 && NK == 9 ? TM_CONTRACT_WAVES : 2))
 void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd, size_t s_stride, const char *l_even,
                 const char *l_odd, size_t l_stride, const uint32_t *codes, double *cpart, int nchunk,
                 size_t part_stride, int n, int total)
@@ -362,16 +361,6 @@ void k_contract(Geom g, const void *G, const char *s_even, const char *s_odd, si
     wave_write32(acc, dst + (K) * 32);
     if constexpr (NK == 1) {
         TMK_KIND(0)
-    } else if constexpr (contract_waves<SPS, NK>() == 1 && NG == 1) {
-        TMK_KIND(0)
-        TMK_KIND(1)
-        TMK_KIND(2)
-        TMK_KIND(3)
-        TMK_KIND(4)
-        TMK_KIND(5)
-        TMK_KIND(6)
-        TMK_KIND(7)
-        TMK_KIND(8)
     } else {
         // wave w of group kg computes kind kg * waves + w
         switch (__builtin_amdgcn_readfirstlane(kg * contract_waves<SPS, NK>() + ((int)threadIdx.x >> 6))) {
@@ -421,7 +410,7 @@ static void contract_t(int sps, const Geom &g, const void *gauge, const char *s_
     const int nchunk = contract_nchunk(g);
     const int lt = g.L[3];
     const size_t ps = contract_part_doubles(g);
-    const int total = lt * nchunk * n * (sps == P32 ? contract_groups<P32, NK>() : 1);
+    const int total = lt * nchunk * n * (sps == P32 ? contract_groups<P32, NK>() : contract_groups<P64, NK>());
     const unsigned nb = (unsigned)(8 * ((total + 7) / 8));
     if (sps == P32)
         hipLaunchKernelGGL((k_contract<P32, FIELD, NK>), dim3(nb), dim3(64 * contract_waves<P32, NK>()), 0, s, g,
