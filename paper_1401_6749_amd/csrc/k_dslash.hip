@@ -726,7 +726,7 @@ __global__ __launch_bounds__(BLOCK, dslash_waves<SP>()) void k_dslash(const Dsla
 // both buffer schemes give the same bits.
 // ---------------------------------------------------------------------------
 #ifndef TM_WALK_MAX_HALF
-#define TM_WALK_MAX_HALF 512
+#define TM_WALK_MAX_HALF 256
 #endif
 #ifndef TM_WALK_MAX_F32
 #define TM_WALK_MAX_F32 256
@@ -755,8 +755,11 @@ constexpr int walk_nbuf()
     return SP == P64 ? TM_WALK_NB_F64 : SP == P32 ? TM_WALK_NB_F32 : 2;
 }
 // largest chunk (threads per block) per storage precision: FP64 256 sites
-// (48 KB, one buffer), FP32 256 (24 KB, one buffer), FP16/BF16 512 (52 KB,
-// two buffers)
+// (48 KB, one buffer), FP32 256 (24 KB, one buffer), FP16/BF16 256 (26 KB,
+// two buffers: 512-site chunks, 52 KB, read fewer halo neighbours, 0.75
+// against 1.0 per site at 32^3x64, but their eight-wave blocks start less
+// readily beside a concurrent stream's kernels: TSM step 273.9 against 278.7
+// sources/s, same bits)
 template <int SP>
 constexpr int walk_max()
 {
