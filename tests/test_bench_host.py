@@ -110,3 +110,30 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr and not r.stdout.strip()
+
+
+def test_committed_bench_line_keeps_the_contract():
+    """The committed bench line (profiles/) carries every field of the output
+    contract, and its figures agree with one another: value from the step
+    time, the roofline fraction from the algorithmic bytes and the launch
+    time, the traffic record keyed to the current Dslash code."""
+    d = json.load(open(os.path.join(ROOT, "profiles", "bench_tsm_32c64_line.json")))
+    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+              "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert k in d, k
+    c = d["config"]
+    assert d["n_gpus"] == 1 and c["workload"] == "tsm-batched-32c64" and c["lattice"] == [32, 32, 32, 64]
+    assert d["value"] == pytest.approx((c["n_hp"] + c["n_lp"]) / (d["ms_per_step"] / 1e3), rel=2e-3)
+    r = d["roofline"]
+    for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert k in r, k
+    assert r["alg_bytes_per_launch"] == 1440 * 32 ** 3 * 64 // 2
+    assert r["achieved"] == pytest.approx(r["alg_bytes_per_launch"] / (r["launch_us"] * 1e-6) / 1e9, rel=2e-3)
+    assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=2e-3) and r["peak"] == 8000.0
+    stale = "the profiles predate the current Dslash code: refresh the bench line and the traffic record"
+    assert r["kernel_hash"] == bench.kernel_hash(), stale
+    traffic = json.load(open(os.path.join(ROOT, "profiles", "dslash_f16_traffic.json")))
+    assert traffic["kernel_hash"] == bench.kernel_hash(), stale
+    assert r["traffic"] == traffic["hbm_bytes_per_launch"]
+    cb = d["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
